@@ -1,0 +1,340 @@
+"""Pins of the CPU oracle against the paper and against independent computations.
+
+Nothing here compares the oracle with itself: the expected values come from the paper's own
+examples (tests/golden/), from Python's ``re`` module applied per document, from the
+generator's rank histogram (no tokeniser involved), from exact-fraction brute force, and from
+invariants that any correct word counter satisfies.
+"""
+import collections
+import itertools
+import json
+import os
+import random
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2206_05269_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+WORD_RE = re.compile(rb"[a-z0-9']+")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def regex_count(docs):
+    """Independent tokeniser: re.findall over each lower-cased document (ASCII-only lower)."""
+    c = collections.Counter()
+    for d in docs:
+        c.update(WORD_RE.findall(bytes(d).lower()))
+    return dict(c)
+
+
+def as_str_dict(t):
+    return {k.decode(): v for k, v in t.as_dict().items()}
+
+
+def join_docs(docs):
+    text = b"".join(docs)
+    off = np.zeros(len(docs) + 1, dtype=np.int64)
+    np.cumsum([len(d) for d in docs], out=off[1:])
+    return text, off
+
+
+# ------------------------------------------------------------------------------------------
+# the paper's worked examples
+# ------------------------------------------------------------------------------------------
+
+def test_section2_worked_example_reduced_table():
+    g = golden("section2_worked_example.json")
+    text, off = join_docs([d.encode() for d in g["docs"]])
+    t = oracle.count(text, off)
+    assert as_str_dict(t) == g["reduced"]
+    assert t.total == g["total_tokens"] == sum(g["reduced"].values())
+
+
+def test_section2_partial_tables_merge_to_reduced_table():
+    g = golden("section2_worked_example.json")
+    parts = [oracle.table_from_dict({k.encode(): v for k, v in p.items()}) for p in g["partials"]]
+    assert as_str_dict(oracle.merge(parts)) == g["reduced"]
+
+
+def test_section2_median_split_reproduces_the_printed_partition():
+    # The two-process method sorts all words (with repeats) and gives each process half.
+    g = golden("section2_worked_example.json")
+    text, off = join_docs([d.encode() for d in g["docs"]])
+    t = oracle.count(text, off)
+    multiset = sorted(w for w, c in t.as_dict().items() for _ in range(c))
+    half = len(multiset) // 2
+    lo = collections.Counter(w.decode() for w in multiset[:half])
+    hi = collections.Counter(w.decode() for w in multiset[half:])
+    assert dict(lo) == g["partials"][0]
+    assert dict(hi) == g["partials"][1]
+
+
+def test_section2_case_and_punctuation():
+    g = golden("section2_case_punct.json")
+    assert as_str_dict(oracle.count(g["text"].encode())) == g["expected"]
+
+
+def test_section3_3_grouped_counts_reduce_to_sum():
+    g = golden("section3_3_grouping.json")
+    w = g["word"].encode()
+    docs = [b" ".join([w] * n) + b"." for n in g["per_doc"]]
+    text, off = join_docs(docs)
+    per = oracle.count(text, off, per_doc=True)
+    assert [int(c) for c in per.counts] == g["per_doc"]
+    assert [int(d) for d in per.docs] == [0, 1, 2]
+    assert oracle.merge([per]).as_dict() == {w: g["reduced"]}
+    assert oracle.count(text, off).as_dict() == {w: g["reduced"]}
+
+
+def test_section4_3_applause_marker():
+    g = golden("section4_3_applause.json")
+    assert as_str_dict(oracle.count(g["text"].encode())) == g["expected"]
+
+
+# ------------------------------------------------------------------------------------------
+# brute force against re, per document
+# ------------------------------------------------------------------------------------------
+
+ALPHABET = [b"a", b"Z", b"0", b"'", b" ", b",", b"\x80", b"\n"]
+
+
+def test_bruteforce_every_short_string_as_its_own_document():
+    docs = [b"".join(p) for n in range(0, 6) for p in itertools.product(ALPHABET, repeat=n)]
+    text, off = join_docs(docs)
+    per = oracle.count(text, off, per_doc=True)
+    got = collections.defaultdict(dict)
+    for (d, w), c in per.as_dict().items():
+        got[d][w] = c
+    want_total = 0
+    for d, doc in enumerate(docs):
+        exp = regex_count([doc])
+        want_total += sum(exp.values())
+        assert got.get(d, {}) == exp, (d, doc)
+    assert per.total == want_total
+
+
+def test_bruteforce_random_text_random_document_splits():
+    for seed in range(6):
+        text = synth.random_text(20_000, seed, alphabet=b"aAzZ09' ,.\x80\xff\n\t-\"")
+        off = synth.random_splits(len(text), 1 + seed * 37, seed + 100)
+        docs = [text[off[i]:off[i + 1]] for i in range(len(off) - 1)]
+        t = oracle.count(text, off)
+        assert t.as_dict() == regex_count(docs)
+        assert t.total == sum(regex_count(docs).values())
+
+
+def test_every_byte_value_classified_like_re():
+    # each of the 256 byte values between two word bytes: joins them or splits them
+    for b in range(256):
+        s = b"q" + bytes([b]) + b"q"
+        assert oracle.count(s).as_dict() == regex_count([s]), b
+
+
+def test_documents_are_hard_delimiters_and_bytes_outside_are_ignored():
+    text = b"xxabcabcyy"
+    off = [2, 5, 8]          # "abc" | "abc"; the x and y bytes are outside every document
+    assert oracle.count(text, off).as_dict() == {b"abc": 2}
+    assert oracle.count(text, [2, 4, 8]).as_dict() == {b"ab": 1, b"cabc": 1}
+
+
+def test_empty_inputs():
+    assert len(oracle.count(b"")) == 0
+    assert oracle.count(b"", [0]).total == 0
+    assert len(oracle.count(b"   ,,. \n")) == 0
+    t = oracle.count(b"a b", [0, 0, 0, 3, 3], per_doc=True)
+    assert t.as_dict() == {(2, b"a"): 1, (2, b"b"): 1}
+
+
+def test_invalid_offsets_are_rejected():
+    with pytest.raises(oracle.OracleError):
+        oracle.count(b"abc", [0, 2, 1])
+    with pytest.raises(oracle.OracleError):
+        oracle.count(b"abc", [0, 4])
+
+
+def test_long_word_has_no_length_cap():
+    w = b"Ab" * 300_000
+    t = oracle.count(b" " + w + b" x " + w.lower())
+    assert t.as_dict() == {w.lower(): 2, b"x": 1}
+
+
+# ------------------------------------------------------------------------------------------
+# the generator's rank histogram is the exact table
+# ------------------------------------------------------------------------------------------
+
+def test_plain_1mb_matches_rank_histogram():
+    c = synth.generate("plain-1MB")
+    t = oracle.count(c.text.numpy(), c.offsets.numpy())
+    assert t.as_dict() == c.expected_table()
+    assert t.total == c.n_tokens == int(c.expected.sum())
+
+
+def test_corpora_match_rank_histograms():
+    for c in synth.generate("corpora-4x2000", scale=0.1):
+        t = oracle.count(c.text.numpy(), c.offsets.numpy())
+        assert t.as_dict() == c.expected_table()
+
+
+def test_stream_piece_matches_rank_histogram():
+    c = synth.generate("stream-8GiB", scale=1 / 1024)
+    t = oracle.count(c.text.numpy(), c.offsets.numpy())
+    assert t.as_dict() == c.expected_table()
+
+
+def test_per_doc_matches_per_doc_rank_histograms():
+    c = synth.generate("batched-100k", scale=0.0005, per_doc_truth=True)
+    t = oracle.count(c.text.numpy(), c.offsets.numpy(), per_doc=True)
+    want = {}
+    for d, h in enumerate(c.doc_expected):
+        h = h.numpy()
+        for k in np.nonzero(h)[0]:
+            want[(d, bytes(c.vocab[k, :c.vocab_lens[k]]))] = int(h[k])
+    assert t.as_dict() == want
+
+
+# ------------------------------------------------------------------------------------------
+# invariants
+# ------------------------------------------------------------------------------------------
+
+def _small_corpus():
+    c = synth.generate("plain-1MB")
+    text = c.text.numpy()[:200_000].tobytes()
+    off = np.array([0, 30_000, 30_000, 95_001, 140_000, 200_000], dtype=np.int64)
+    return text, off
+
+
+def _token_starts(text, off):
+    """Token count from word-start positions, computed with numpy byte classes."""
+    a = np.frombuffer(text, dtype=np.uint8)
+    low = np.where((a >= 65) & (a <= 90), a + 32, a)
+    w = ((low >= 97) & (low <= 122)) | ((low >= 48) & (low <= 57)) | (low == 39)
+    prev = np.concatenate([[False], w[:-1]])
+    start = np.zeros(len(a), dtype=bool)
+    start[off[:-1][off[:-1] < len(a)]] = True
+    inside = np.zeros(len(a) + 1, dtype=np.int64)
+    np.add.at(inside, off[:-1], 1)
+    np.add.at(inside, off[1:], -1)
+    inside = np.cumsum(inside)[:-1] > 0
+    return int((w & inside & (~prev | start)).sum())
+
+
+def test_sum_of_counts_equals_token_count():
+    text, off = _small_corpus()
+    t = oracle.count(text, off)
+    assert int(t.counts.sum()) == t.total == _token_starts(text, off)
+
+
+def test_merge_of_per_doc_tables_equals_count_of_concatenation():
+    text, off = _small_corpus()
+    per = oracle.count(text, off, per_doc=True)
+    whole = oracle.count(text, off)
+    assert oracle.merge([per]).as_dict() == whole.as_dict()
+    singles = [oracle.count(text[off[i]:off[i + 1]]) for i in range(len(off) - 1)]
+    assert oracle.merge(singles).as_dict() == whole.as_dict()
+
+
+def test_permuting_documents_changes_nothing():
+    text, off = _small_corpus()
+    docs = [text[off[i]:off[i + 1]] for i in range(len(off) - 1)]
+    random.Random(3).shuffle(docs)
+    t2, off2 = join_docs(docs)
+    assert oracle.count(t2, off2).as_dict() == oracle.count(text, off).as_dict()
+
+
+def test_upper_case_changes_nothing():
+    text, off = _small_corpus()
+    assert oracle.count(text.upper(), off).as_dict() == oracle.count(text, off).as_dict()
+
+
+def test_extra_delimiters_change_nothing():
+    text, off = _small_corpus()
+    a = np.frombuffer(text, dtype=np.uint8)
+    low = np.where((a >= 65) & (a <= 90), a + 32, a)
+    w = ((low >= 97) & (low <= 122)) | ((low >= 48) & (low <= 57)) | (low == 39)
+    # repeat every delimiter byte three times inside each document
+    docs = []
+    for i in range(len(off) - 1):
+        seg = a[off[i]:off[i + 1]]
+        rep = np.where(w[off[i]:off[i + 1]], 1, 3)
+        docs.append(np.repeat(seg, rep).tobytes())
+    t2, off2 = join_docs(docs)
+    assert oracle.count(t2, off2).as_dict() == oracle.count(text, off).as_dict()
+
+
+def test_doubling_the_corpus_doubles_every_count():
+    text, off = _small_corpus()
+    one = oracle.count(text, off).as_dict()
+    two = oracle.count(text + text, np.concatenate([off, off[1:] + len(text)])).as_dict()
+    assert two == {k: 2 * v for k, v in one.items()}
+
+
+def test_merge_is_associative_and_commutative():
+    text, off = _small_corpus()
+    ts = [oracle.count(text[off[i]:off[i + 1]]) for i in range(len(off) - 1)]
+    a = oracle.merge([oracle.merge(ts[:2]), oracle.merge(ts[2:])]).as_dict()
+    b = oracle.merge(list(reversed(ts))).as_dict()
+    assert a == b == oracle.count(text, off).as_dict()
+
+
+# ------------------------------------------------------------------------------------------
+# top-k ratio against an exact-fraction brute force
+# ------------------------------------------------------------------------------------------
+
+def brute_topk(dicts, k, min_count=1):
+    vocab = sorted(set().union(*[d.keys() for d in dicts]))
+    V = len(vocab)
+    N = [sum(d.values()) for d in dicts]
+    out = []
+    for c, d in enumerate(dicts):
+        rows = []
+        for w in vocab:
+            nc = d.get(w, 0)
+            if nc < max(min_count, 1):
+                continue
+            nr = sum(o.get(w, 0) for j, o in enumerate(dicts) if j != c)
+            rows.append((-Fraction(nc + 1, nr + 1), -nc, w, nc, nr))
+        rows.sort()
+        Nr = sum(N) - N[c]
+        out.append([(w, nc, nr, float(Fraction(nc + 1, N[c] + V) / Fraction(nr + 1, Nr + V)))
+                    for _, _, w, nc, nr in rows[:k]])
+    return out, V
+
+
+def _check_topk(dicts, k, min_count=1):
+    tabs = [oracle.table_from_dict(d) for d in dicts]
+    got = oracle.topk_ratio(tabs, k, min_count)
+    want, V = brute_topk(dicts, k, min_count)
+    assert got.vocab_size == V
+    for c in range(len(dicts)):
+        assert got.words[c] == [w for w, _, _, _ in want[c]]
+        assert list(map(int, got.n_c[c])) == [nc for _, nc, _, _ in want[c]]
+        assert list(map(int, got.n_rest[c])) == [nr for _, _, nr, _ in want[c]]
+        np.testing.assert_allclose(got.score[c], [s for *_, s in want[c]], rtol=1e-12)
+
+
+def test_topk_random_small_tables_with_ties():
+    rng = random.Random(11)
+    words = [bytes(rng.choice(b"abc") for _ in range(rng.randint(1, 3))) for _ in range(60)]
+    for trial in range(20):
+        dicts = []
+        for c in range(rng.randint(1, 5)):
+            d = {}
+            for w in rng.sample(words, rng.randint(0, 20)):
+                d[w] = rng.randint(1, 4)
+            dicts.append(d)
+        _check_topk(dicts, rng.randint(1, 12), rng.randint(0, 3))
+
+
+def test_topk_generated_corpora():
+    cs = synth.generate("corpora-4x2000", scale=0.05)
+    dicts = [oracle.count(c.text.numpy(), c.offsets.numpy()).as_dict() for c in cs]
+    _check_topk(dicts, 50)
