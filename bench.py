@@ -1,0 +1,138 @@
+"""Benchmark: word-count throughput on one MI355X, as GB/s of text and fraction of HBM peak.
+
+Workload "stream-8GiB": one 8 GiB document of Zipf(s = 1.0) text over a 1,000,000-word
+vocabulary (lengths 1..16), generated on the GPU from a fixed seed; global table of 2^22
+slots; int64 counts. One step = one wc_count call: clear the table, scan and count the whole
+corpus, compact the table into (word, count) arrays, read the sizes back. The corpus is
+resident in HBM before timing starts.
+
+Prints one JSON line (rank 0). Runs on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "stream-8GiB"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(corpus, sample_bytes: int):
+    """Time the oracle (single-threaded CPU) on the first sample_bytes of the corpus."""
+    import numpy as np
+    import oracle
+    host = corpus[:sample_bytes].cpu().numpy()
+    # cut at a delimiter so the sample is a prefix of whole tokens
+    oracle.lib()
+    t0 = time.perf_counter()
+    t = oracle.count(host, np.array([0, len(host)], dtype=np.int64))
+    dt = time.perf_counter() - t0
+    return {"value": round(len(host) / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {len(host)} bytes of the {WORKLOAD} corpus "
+                      f"({t.total} tokens, {len(t)} words) in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 8 GiB corpus")
+    ap.add_argument("--cpu-sample-mb", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the counter would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2206_05269_amd import synth, wc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.WORKLOADS[WORKLOAD]
+    t0 = time.perf_counter()
+    log(f"generating {WORKLOAD} (scale {args.scale}) on {dev}")
+    c = synth.generate(WORKLOAD, device=dev, scale=args.scale,
+                       progress=lambda done, total: None)
+    torch.cuda.synchronize()
+    B = c.text.numel()
+    log(f"generated {B} bytes, {c.n_tokens} tokens in {time.perf_counter() - t0:.1f} s")
+
+    slots = w.table_slots
+    plan = wc.count_plan(B, 1, count_bytes=w.count_bytes, table_slots=slots)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    kw = dict(count_bytes=w.count_bytes, table_slots=slots, workspace=ws, regrow=False,
+              debug_flags=wc.WC_DEBUG_TIME)
+
+    for i in range(args.warmup):
+        r = wc.count(c.text, c.offsets, **kw)
+        log(f"warmup {i}: {r.res.total_ms:.3f} ms (count kernel {r.res.kernel_ms:.3f} ms)")
+    # correctness guard: totals must match the generator
+    r = wc.count(c.text, c.offsets, **kw)
+    n_words = int((c.expected > 0).sum())
+    if r.total_tokens != c.n_tokens or r.n_entries != n_words:
+        log(f"MISMATCH tokens {r.total_tokens} vs {c.n_tokens}, words {r.n_entries} vs {n_words}")
+        sys.exit(1)
+
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = wc.count(c.text, c.offsets, **kw)
+        kernel_ms.append(r.res.kernel_ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / args.steps
+    gbs = B / (dt / args.steps) / 1e9
+    k_avg = sum(kernel_ms) / len(kernel_ms)
+    D = r.n_entries
+    alg_bytes = B + D * 32          # text read once + final table written once (32 B slots)
+    achieved = alg_bytes / (k_avg * 1e-3) / 1e9
+    log(f"step {ms_step:.3f} ms, {gbs:.1f} GB/s; count kernel avg {k_avg:.3f} ms "
+        f"({achieved:.1f} GB/s algorithmic)")
+
+    out = {
+        "metric": "word-count GB/s of text (fraction of HBM peak)",
+        "value": round(gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (seeded Zipf text generated on the GPU)",
+        "config": {"workload": WORKLOAD, "bytes": B, "tokens": c.n_tokens, "words": D,
+                   "vocab": w.vocab, "zipf_s": w.zipf_s, "max_word_len": w.max_len,
+                   "table_slots": slots, "count_bytes": w.count_bytes},
+        "tokens_per_s": round(c.n_tokens / (dt / args.steps), 1),
+        "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "count_kernel",
+                     "kernel_ms": round(k_avg, 4)},
+    }
+    if not args.no_cpu:
+        sample = min(B, args.cpu_sample_mb << 20)
+        log(f"timing the oracle on {sample} bytes")
+        out["cpu_baseline"] = cpu_baseline(c.text, sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * wc.h - C ABI of libwc, a word-frequency counter for AMD MI355X (gfx950).
+ *
+ * The operations follow "MapReduce for Counting Word Frequencies with MPI and GPUs":
+ *   - map: lower-case the text, drop punctuation, split it into words and count each word
+ *     per document (Section 2, Section 3.1);
+ *   - reduce: sum the per-document counts of each word (Section 3.2, Section 3.3);
+ *   - per-corpus comparison: find the words one corpus uses distinctly more often than the
+ *     others (Section 4.3).
+ * The whole map and reduce run on the GPU (the direction of Section 5.2): HIP kernels scan
+ * the bytes, hash each word with FNV-1a 64, aggregate counts in per-workgroup LDS tables and
+ * merge them into one open-addressing table in device memory.
+ *
+ * Tokeniser (the paper deletes punctuation before splitting; here every byte outside the
+ * word alphabet is a delimiter, which agrees wherever punctuation only separates words):
+ *   fold(x) = x + 32 for 'A'..'Z', else x (ASCII only);
+ *   a byte is a word byte when fold(x) is in 'a'..'z', '0'..'9' or '\'';
+ *   a token is a maximal run of word bytes inside one document; its word is the folded run.
+ * Document d is bytes [offsets[d], offsets[d+1]) of the corpus; offsets must be
+ * non-decreasing and offsets[n_docs] <= corpus_len; bytes outside [offsets[0],
+ * offsets[n_docs]) are ignored; empty documents are allowed; a word never spans two
+ * documents and has no length limit. Counts are exact: never approximated or dropped.
+ *
+ * Memory and streams. Every device buffer is owned by the caller (the Python binding uses
+ * PyTorch tensors). The library allocates no device memory in wc_count / wc_merge /
+ * wc_topk_ratio and keeps no pointer after they return; their outputs live inside the
+ * caller's workspace. Work is enqueued on the caller's stream, passed as void* (a
+ * hipStream_t; NULL = the null stream). These calls synchronise that stream once before
+ * returning (to read sizes and error flags) and are safe to call from several host threads
+ * on different streams and workspaces.
+ *
+ * Errors: every call returns a wc_status. Device errors return WC_EDEVICE and
+ * wc_last_hip_error() gives the hipError_t of the calling thread's last failure.
+ */
+#ifndef WC_H
+#define WC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wc_status;
+#define WC_OK          0
+#define WC_EINVAL     -1  /* bad argument: null pointer, non-monotone offsets, bad k, ... */
+#define WC_ENOMEM     -2  /* workspace too small, or a request over the memory budget */
+#define WC_ETABLEFULL -3  /* hash table full: rerun with more slots (the binding doubles) */
+#define WC_EOVERFLOW  -4  /* a count does not fit the requested count width */
+#define WC_EDEVICE    -5  /* HIP error; see wc_last_hip_error() */
+#define WC_EAGAIN     -6  /* not ready yet (server) */
+
+/* counting modes */
+#define WC_GLOBAL  0u  /* one table over all documents */
+#define WC_PER_DOC 1u  /* one table per document, returned as CSR over documents */
+
+/* flush policies of the per-workgroup LDS table */
+#define WC_FLUSH_ALL    0u  /* when the LDS table passes its load limit, flush all of it */
+#define WC_FLUSH_BYPASS 1u  /* never flush early; a word that finds no LDS slot goes global */
+
+/* debug flags (wc_opts.debug_flags) */
+#define WC_DEBUG_TIME   1u  /* time the count kernel with HIP events (wc_result.kernel_ms) */
+#define WC_DEBUG_NO_LDS 2u  /* skip the LDS table: every token goes to the global table */
+
+/* Launch tuning; a zero field takes the library default. */
+typedef struct wc_tuning {
+  uint32_t stage_bytes;   /* bytes one workgroup scans per step: 4096 or 8192 (= 16 B/thread) */
+  uint32_t lds_entries;   /* LDS table entries per workgroup, power of two, 256..4096 */
+  uint32_t flush_policy;  /* WC_FLUSH_ALL or WC_FLUSH_BYPASS */
+  uint32_t grid_blocks;   /* workgroups in the count launch (0 = 2 per CU) */
+  uint32_t lds_load_pct;  /* WC_FLUSH_ALL: flush when the LDS table is this % full (0 = 50) */
+  uint32_t reserved;
+} wc_tuning;
+
+typedef struct wc_opts {
+  uint32_t count_bytes;      /* width of exported counts: 4 (int32) or 8 (int64) */
+  uint32_t mode;             /* WC_GLOBAL or WC_PER_DOC */
+  uint64_t table_slots;      /* global table slots, power of two; 0 = sized from the input */
+  const wc_tuning* tuning;   /* NULL = defaults */
+  uint32_t debug_flags;      /* WC_DEBUG_* */
+  uint32_t debug_hash_bits;  /* 0 = full 64-bit keys; 1..63 keep only the low bits of every
+                                key, forcing key collisions so the byte compare decides */
+  uint64_t word_bytes_cap;   /* capacity reserved for exported word bytes; 0 = auto */
+} wc_opts;
+
+typedef struct wc_plan {
+  uint64_t table_slots;      /* slots the call will use */
+  uint64_t workspace_bytes;  /* bytes of device workspace to pass */
+  uint64_t max_entries;      /* capacity of the exported arrays (= table_slots) */
+  uint64_t word_bytes_cap;   /* capacity of the exported word bytes */
+} wc_plan;
+
+/* A word table in device memory: entry e is the folded word
+ * d_words[d_word_offsets[e] .. d_word_offsets[e+1]) with count d_counts[e]. Entry order is
+ * unspecified. Per-document tables are grouped by document: entries of document d are
+ * [d_doc_ptr[d], d_doc_ptr[d+1]) and d_docs[e] is the entry's document. */
+typedef struct wc_result {
+  uint64_t n_entries;
+  uint64_t total_tokens;     /* tokens counted (= sum of counts) */
+  uint64_t word_bytes;       /* = d_word_offsets[n_entries] */
+  uint64_t n_docs;           /* documents (per-document tables) */
+  uint64_t table_slots;      /* slots of the table the result was compacted from */
+  uint32_t count_bytes;      /* 4 or 8 */
+  uint32_t mode;             /* WC_GLOBAL or WC_PER_DOC */
+  uint64_t* d_word_offsets;  /* uint64[n_entries + 1] */
+  uint8_t* d_words;          /* uint8[word_bytes] */
+  void* d_counts;            /* int32 or int64 [n_entries] */
+  uint64_t* d_doc_ptr;       /* WC_PER_DOC: uint64[n_docs + 1], else NULL */
+  uint64_t* d_docs;          /* WC_PER_DOC: uint64[n_entries], else NULL */
+  float kernel_ms;           /* WC_DEBUG_TIME: duration of the count (or merge) kernel */
+  float total_ms;            /* WC_DEBUG_TIME: duration of the whole call on the device */
+} wc_result;
+
+/* Text of a status code (static storage). */
+const char* wc_strerror(wc_status s);
+
+/* hipError_t of the calling thread's last WC_EDEVICE. */
+int32_t wc_last_hip_error(void);
+
+/* Plan a wc_count call: slots, workspace bytes and output capacities for a corpus of
+ * corpus_len bytes in n_docs documents. No device work. Returns WC_EINVAL for bad options. */
+wc_status wc_count_plan(uint64_t corpus_len, uint64_t n_docs, const wc_opts* opts,
+                        wc_plan* out);
+
+/* Count the words of a device-resident corpus (Section 3.1 map + Section 3.2 reduce, fused).
+ *   d_corpus     device uint8[corpus_len], any alignment; not modified.
+ *   d_offsets    device uint64[n_docs + 1] document offsets (see the top of this file).
+ *   d_workspace  device buffer of at least wc_count_plan(...).workspace_bytes bytes; it holds
+ *                the hash table and the exported arrays that *out points into, so it must
+ *                outlive every use of *out.
+ *   out          filled on WC_OK (device pointers into d_workspace + host-side sizes).
+ * Errors: WC_EINVAL (null pointer with non-zero size, bad options, invalid offsets),
+ * WC_ENOMEM (workspace smaller than planned, or more word bytes than word_bytes_cap; then
+ * out->word_bytes holds the bytes needed), WC_ETABLEFULL (more distinct words than the table
+ * takes at a load of 7/8; rerun with more slots), WC_EOVERFLOW (count_bytes = 4 and a count
+ * above INT32_MAX), WC_EDEVICE. */
+wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t* d_offsets,
+                   uint64_t n_docs, const wc_opts* opts, void* d_workspace,
+                   uint64_t workspace_bytes, wc_result* out, void* stream);
+
+/* Plan a wc_merge of k tables (Section 3.3: the grouped counts of each word are summed).
+ * Uses the inputs' host-side sizes only. */
+wc_status wc_merge_plan(const wc_result* const* tables, uint32_t k, const wc_opts* opts,
+                        wc_plan* out);
+
+/* Merge k tables into one global table holding the pointwise sum of counts over the union of
+ * words (per-document inputs are summed over their documents). Inputs are untouched and must
+ * stay valid during the call; the result lives in d_workspace. Associative and commutative;
+ * merging per-document tables equals counting the concatenation. Errors as wc_count. */
+wc_status wc_merge(const wc_result* const* tables, uint32_t k, const wc_opts* opts,
+                   void* d_workspace, uint64_t workspace_bytes, wc_result* out, void* stream);
+
+/* Per-corpus distinctive words (Section 4.3 compares presidents by the words each uses more
+ * than the others). Over n corpora with joint vocabulary V (the union of their words): for
+ * corpus c and word w with n_c(w) >= max(min_count, 1), n_R(w) = the other corpora's count;
+ * words are ranked by (n_c+1)/(n_R+1) descending, compared exactly, then n_c descending, then
+ * word bytes ascending (unsigned, a proper prefix first); a total order, so the answer is
+ * unique. score = ((n_c+1)/(N_c+V)) / ((n_R+1)/(N_R+V)) in double, N_c = tokens of corpus
+ * c, N_R = tokens of the others. Row r of corpus c is at index c*k + r; n_rows[c] <= k rows
+ * are valid (fewer when fewer words are eligible). */
+typedef struct wc_topk {
+  uint32_t n_corpora;
+  uint32_t k;
+  uint64_t vocab_size;       /* V */
+  uint64_t* d_word_offsets;  /* uint64[n_corpora*k + 1]: row words in d_words */
+  uint8_t* d_words;          /* folded words of the rows, row-major */
+  uint64_t* d_n_c;           /* uint64[n_corpora*k] */
+  uint64_t* d_n_rest;        /* uint64[n_corpora*k] */
+  double* d_score;           /* double[n_corpora*k] */
+  uint64_t n_rows[64];       /* host: valid rows per corpus */
+  uint64_t word_bytes;       /* host: bytes used in d_words */
+} wc_topk;
+
+/* Plan wc_topk_ratio: workspace bytes for n corpora (at most 64) and k rows per corpus
+ * (1 <= k <= 4096). */
+wc_status wc_topk_ratio_plan(const wc_result* const* corpora, uint32_t n_corpora, uint32_t k,
+                             uint64_t* workspace_bytes);
+
+/* Top-k distinctive words per corpus (see wc_topk). Inputs are global word tables (for
+ * example wc_count results of each corpus). Errors: WC_EINVAL (n_corpora 0 or > 64, k 0 or
+ * > 4096, null pointers), WC_ENOMEM, WC_EDEVICE. */
+wc_status wc_topk_ratio(const wc_result* const* corpora, uint32_t n_corpora, uint32_t k,
+                        uint64_t min_count, void* d_workspace, uint64_t workspace_bytes,
+                        wc_topk* out, void* stream);
+
+/* FNV-1a 64 (Fowler, Noll, Vo) of n byte strings on the device: d_out[i] = FNV-1a 64 of
+ * fold(d_bytes[d_offsets[i] .. d_offsets[i+1])), computed by the same device function the
+ * counter uses (offset basis 0xcbf29ce484222325, prime 0x100000001b3; a result of 0 is
+ * stored as 1 since 0 marks an empty slot). Exposed so the hash can be checked against
+ * published test vectors. */
+wc_status wc_hash_words(const uint8_t* d_bytes, const uint64_t* d_offsets, uint64_t n,
+                        uint64_t* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WC_H */

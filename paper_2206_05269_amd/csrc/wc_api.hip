@@ -1,0 +1,682 @@
+// Host side of the C ABI declared in include/wc.h: argument checks, workspace layout,
+// kernel launches on the caller's stream, and the single synchronisation that reads sizes
+// and error flags back.
+#include <string.h>
+
+#include <algorithm>
+
+#include "wc_internal.h"
+
+using namespace wc;
+
+namespace {
+
+thread_local int32_t g_last_hip = 0;
+
+constexpr uint64_t kAlign = 256;
+constexpr uint32_t kDefaultLds = 2048;
+constexpr uint32_t kDefaultBlock = 512;
+
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) {                           \
+      g_last_hip = (int32_t)e_;                       \
+      return WC_EDEVICE;                              \
+    }                                                 \
+  } while (0)
+
+// Bump allocation inside the caller's workspace (base may be null when only sizing).
+struct Bump {
+  uint8_t* base;
+  uint64_t off = 0;
+  explicit Bump(void* b) : base((uint8_t*)b) {}
+  template <class T>
+  T* take(uint64_t bytes) {
+    uint64_t o = off;
+    off = align_up(off + bytes);
+    return base ? (T*)(base + o) : (T*)nullptr;
+  }
+};
+
+struct Tune {
+  uint32_t block, stage, lds, policy, grid, flush_at;
+};
+
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+bool resolve_tuning(const wc_tuning* t, Tune* out) {
+  Tune u;
+  u.stage = t && t->stage_bytes ? t->stage_bytes : kDefaultBlock * 16;
+  if (u.stage != 4096 && u.stage != 8192) return false;
+  u.block = u.stage / 16;
+  u.lds = t && t->lds_entries ? t->lds_entries : kDefaultLds;
+  if (!is_pow2(u.lds) || u.lds < 256 || u.lds > 4096) return false;
+  u.policy = t ? t->flush_policy : WC_FLUSH_ALL;
+  if (u.policy > WC_FLUSH_BYPASS) return false;
+  u.grid = t ? t->grid_blocks : 0;
+  uint32_t pct = t && t->lds_load_pct ? t->lds_load_pct : 50;
+  if (pct > 100) return false;
+  u.flush_at = (uint32_t)((uint64_t)u.lds * pct / 100);
+  *out = u;
+  return true;
+}
+
+bool opts_ok(const wc_opts* o) {
+  if (!o) return false;
+  if (o->count_bytes != 4 && o->count_bytes != 8) return false;
+  if (o->mode != WC_GLOBAL && o->mode != WC_PER_DOC) return false;
+  if (o->table_slots && (!is_pow2(o->table_slots) || o->table_slots < 64)) return false;
+  if (o->debug_hash_bits > 63) return false;
+  return true;
+}
+
+uint64_t key_mask_of(const wc_opts* o) {
+  return o->debug_hash_bits ? ((1ull << o->debug_hash_bits) - 1) : ~0ull;
+}
+
+struct CountLayout {
+  uint64_t S, n_stages, n_blocks, word_cap;
+  size_t sort_bytes = 0, scan_bytes = 0;
+  Header* hdr;
+  Slot* table;
+  uint64_t* stage_doc;
+  uint64_t* bsum;
+  uint64_t* woff;
+  void* counts;
+  uint8_t* words;
+  // per-document
+  uint64_t *docs, *doc_ptr, *list_docs, *list_slots, *sorted_docs, *sorted_slots, *lens;
+  void* cub;
+  uint64_t total;
+};
+
+int64_t base_offset(const uint8_t* corpus) {
+  return -(int64_t)((uintptr_t)corpus & 15);
+}
+
+bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& tu,
+                  const uint8_t* corpus, void* ws, CountLayout* L) {
+  const bool per_doc = o->mode == WC_PER_DOC;
+  uint64_t S = o->table_slots;
+  if (!S) {
+    uint64_t want = per_doc ? len / 8 : len / 32;
+    want = std::max<uint64_t>(want, 4096);
+    want = std::min<uint64_t>(want, per_doc ? (1ull << 28) : (1ull << 22));
+    S = next_pow2(want);
+  }
+  L->S = S;
+  int64_t b0 = corpus ? base_offset(corpus) : -15;
+  L->n_stages = len ? (uint64_t)(((int64_t)len - b0 + tu.stage - 1) / tu.stage) : 0;
+  L->n_blocks = (S + kExportSpan - 1) / kExportSpan;
+  uint64_t cap = o->word_bytes_cap;
+  if (!cap) cap = std::min<uint64_t>(len, std::max<uint64_t>(S * 24, 1ull << 20));
+  L->word_cap = std::max<uint64_t>(cap, 16);
+  Bump B(ws);
+  L->hdr = B.take<Header>(sizeof(Header));
+  L->table = B.take<Slot>(S * sizeof(Slot));
+  L->stage_doc = B.take<uint64_t>((L->n_stages + 2) * 8);
+  L->bsum = B.take<uint64_t>(L->n_blocks * 16);
+  L->woff = B.take<uint64_t>((S + 1) * 8);
+  L->counts = B.take<uint8_t>(S * o->count_bytes);
+  L->words = B.take<uint8_t>(L->word_cap);
+  L->docs = L->doc_ptr = L->list_docs = L->list_slots = L->sorted_docs = L->sorted_slots =
+      L->lens = nullptr;
+  L->cub = nullptr;
+  if (per_doc) {
+    L->docs = B.take<uint64_t>(S * 8);
+    L->doc_ptr = B.take<uint64_t>((n_docs + 1) * 8);
+    L->list_docs = B.take<uint64_t>(S * 8);
+    L->list_slots = B.take<uint64_t>(S * 8);
+    L->sorted_docs = B.take<uint64_t>(S * 8);
+    L->sorted_slots = B.take<uint64_t>(S * 8);
+    L->lens = B.take<uint64_t>((S + 1) * 8);
+    size_t a = 0, b = 0;
+    if (sort_pairs_u64(nullptr, &a, nullptr, nullptr, nullptr, nullptr, S, 64, 0) != hipSuccess)
+      return false;
+    if (excl_sum_u64(nullptr, &b, nullptr, nullptr, S + 1, 0) != hipSuccess) return false;
+    L->sort_bytes = a;
+    L->scan_bytes = b;
+    L->cub = B.take<uint8_t>(std::max(a, b));
+  }
+  L->total = B.off;
+  return true;
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr, c = nullptr, d = nullptr;
+  bool on = false;
+  hipError_t init(bool enable) {
+    on = enable;
+    if (!on) return hipSuccess;
+    hipError_t e;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&c)) != hipSuccess) return e;
+    return hipEventCreate(&d);
+  }
+  ~Timer() {
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+    if (c) hipEventDestroy(c);
+    if (d) hipEventDestroy(d);
+  }
+};
+
+hipError_t ensure_smem_attr() {
+  static hipError_t once = [] {
+    hipError_t e = set_count_smem(512, 160 * 1024 - 40 * 1024);
+    if (e == hipSuccess) e = set_count_smem(256, 160 * 1024 - 24 * 1024);
+    return e;
+  }();
+  return once;
+}
+
+wc_status finish_flags(const Header& h) {
+  if (h.flags & kFlagBadOffsets) return WC_EINVAL;
+  if (h.flags & kFlagTableFull) return WC_ETABLEFULL;
+  if (h.flags & kFlagWordCap) return WC_ENOMEM;
+  if (h.flags & kFlagCountOverflow) return WC_EOVERFLOW;
+  return WC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wc_strerror(wc_status s) {
+  switch (s) {
+    case WC_OK: return "ok";
+    case WC_EINVAL: return "invalid argument";
+    case WC_ENOMEM: return "workspace too small or over the memory budget";
+    case WC_ETABLEFULL: return "hash table full; use more slots";
+    case WC_EOVERFLOW: return "count does not fit the requested width";
+    case WC_EDEVICE: return "HIP error";
+    case WC_EAGAIN: return "not ready";
+    default: return "unknown status";
+  }
+}
+
+int32_t wc_last_hip_error(void) { return g_last_hip; }
+
+wc_status wc_count_plan(uint64_t corpus_len, uint64_t n_docs, const wc_opts* opts,
+                        wc_plan* out) {
+  if (!opts_ok(opts) || !out) return WC_EINVAL;
+  Tune tu;
+  if (!resolve_tuning(opts->tuning, &tu)) return WC_EINVAL;
+  if (opts->mode == WC_PER_DOC && n_docs >= 0xffffffffull) return WC_EINVAL;
+  CountLayout L;
+  if (!layout_count(corpus_len, n_docs, opts, tu, nullptr, nullptr, &L)) return WC_EDEVICE;
+  out->table_slots = L.S;
+  out->workspace_bytes = L.total + kAlign;  // room for any corpus alignment
+  out->max_entries = L.S;
+  out->word_bytes_cap = L.word_cap;
+  return WC_OK;
+}
+
+wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t* d_offsets,
+                   uint64_t n_docs, const wc_opts* opts, void* d_workspace,
+                   uint64_t workspace_bytes, wc_result* out, void* stream) {
+  if (!opts_ok(opts) || !out || !d_workspace) return WC_EINVAL;
+  if (corpus_len && !d_corpus) return WC_EINVAL;
+  if (!d_offsets) return WC_EINVAL;
+  Tune tu;
+  if (!resolve_tuning(opts->tuning, &tu)) return WC_EINVAL;
+  const bool per_doc = opts->mode == WC_PER_DOC;
+  if (per_doc && n_docs >= 0xffffffffull) return WC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  CountLayout L;
+  if (!layout_count(corpus_len, n_docs, opts, tu, d_corpus, d_workspace, &L)) return WC_EDEVICE;
+  if (L.total > workspace_bytes) return WC_ENOMEM;
+  HIPCHK(ensure_smem_attr());
+
+  Timer tm;
+  HIPCHK(tm.init(opts->debug_flags & WC_DEBUG_TIME));
+  if (tm.on) HIPCHK(hipEventRecord(tm.c, s));
+
+  HIPCHK(launch_fill_zero(L.hdr, sizeof(Header), s));
+  HIPCHK(launch_fill_zero(L.table, L.S * sizeof(Slot), s));
+  const uint64_t occ_limit = L.S - L.S / 8;
+  if (corpus_len && n_docs) {
+    HIPCHK(launch_validate(d_offsets, n_docs, corpus_len, L.hdr, s));
+    const int64_t b0 = base_offset(d_corpus);
+    HIPCHK(launch_stage_doc(d_offsets, n_docs, b0, tu.stage, L.n_stages, L.stage_doc, s));
+    CountParams P;
+    P.corpus = d_corpus;
+    P.len = corpus_len;
+    P.offsets = d_offsets;
+    P.n_docs = n_docs;
+    P.R0 = 0;
+    P.R1 = 0;
+    P.table = L.table;
+    P.mask = L.S - 1;
+    P.occ_limit = occ_limit;
+    P.key_mask = key_mask_of(opts);
+    P.hdr = L.hdr;
+    P.stage_doc = L.stage_doc;
+    P.base_off = b0;
+    P.n_stages = L.n_stages;
+    uint32_t grid = tu.grid ? tu.grid : (uint32_t)device_cus() * 2;
+    if (grid > L.n_stages) grid = (uint32_t)L.n_stages;
+    P.stages_per_wg = (L.n_stages + grid - 1) / grid;
+    grid = (uint32_t)((L.n_stages + P.stages_per_wg - 1) / P.stages_per_wg);
+    P.lds_entries = tu.lds;
+    P.lds_flush_at = tu.flush_at;
+    P.policy = tu.policy;
+    P.no_lds = (opts->debug_flags & WC_DEBUG_NO_LDS) ? 1u : 0u;
+    size_t dyn = (size_t)tu.lds * (per_doc ? 24 : 20);
+    if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
+    HIPCHK(launch_count(P, per_doc, grid, tu.block, dyn, s));
+    if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
+  }
+
+  ExportParams E;
+  memset(&E, 0, sizeof(E));
+  E.table = L.table;
+  E.slots = L.S;
+  E.hdr = L.hdr;
+  E.block_sums = L.bsum;
+  E.n_blocks = L.n_blocks;
+  E.count_bytes = opts->count_bytes;
+  E.per_doc = per_doc ? 1u : 0u;
+  if (!per_doc) {
+    E.word_offsets = L.woff;
+    E.words = L.words;
+    E.word_cap = L.word_cap;
+    E.counts = L.counts;
+    HIPCHK(launch_export(E, s));
+  } else {
+    E.word_cap = ~0ull;
+    E.docs = L.list_docs;
+    E.slot_of_entry = L.list_slots;
+    HIPCHK(launch_export_list(E, s));
+  }
+  Header h;
+  HIPCHK(hipMemcpyAsync(&h, L.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h.flags & (kFlagBadOffsets | kFlagTableFull)) return finish_flags(h);
+
+  memset(out, 0, sizeof(*out));
+  out->n_entries = h.n_entries;
+  out->total_tokens = h.total_tokens;
+  out->n_docs = n_docs;
+  out->table_slots = L.S;
+  out->count_bytes = opts->count_bytes;
+  out->mode = opts->mode;
+  out->d_word_offsets = L.woff;
+  out->d_words = L.words;
+  out->d_counts = L.counts;
+
+  if (per_doc) {
+    const uint64_t n = h.n_entries;
+    // group entries by document: radix sort (document, slot) pairs
+    int end_bit = 1;
+    while (end_bit < 64 && (n_docs >> end_bit)) ++end_bit;
+    size_t tb = L.sort_bytes;
+    if (n) {
+      HIPCHK(sort_pairs_u64(L.cub, &tb, L.list_docs, L.sorted_docs, L.list_slots, L.sorted_slots,
+                            n, end_bit, s));
+    }
+    HIPCHK(launch_doc_csr(L.sorted_docs, n, L.hdr, n_docs, L.doc_ptr, s));
+    HIPCHK(launch_slot_lens(L.table, L.sorted_slots, n, L.lens, s));
+    size_t sb = L.scan_bytes;
+    HIPCHK(excl_sum_u64(L.cub, &sb, L.lens, L.woff, n + 1, s));
+    uint64_t wb = 0;
+    HIPCHK(hipMemcpyAsync(&wb, L.woff + n, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (wb > L.word_cap) {
+      out->word_bytes = wb;
+      return WC_ENOMEM;
+    }
+    HIPCHK(launch_slot_write(L.table, L.sorted_slots, n, L.woff, L.words, L.counts,
+                             opts->count_bytes, L.docs, L.hdr, s));
+    HIPCHK(hipMemcpyAsync(&h, L.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h.word_bytes = wb;
+    out->d_doc_ptr = L.doc_ptr;
+    out->d_docs = L.docs;
+  }
+  out->word_bytes = h.word_bytes;
+  if (tm.on) {
+    HIPCHK(hipEventRecord(tm.d, s));
+    HIPCHK(hipEventSynchronize(tm.d));
+    float ms = 0;
+    if (corpus_len && n_docs) {
+      HIPCHK(hipEventElapsedTime(&ms, tm.a, tm.b));
+      out->kernel_ms = ms;
+    }
+    HIPCHK(hipEventElapsedTime(&ms, tm.c, tm.d));
+    out->total_ms = ms;
+  }
+  return finish_flags(h);
+}
+
+// ------------------------------------------------------------------------------------------
+// merge
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct MergeLayout {
+  uint64_t S, n_blocks, word_cap, total;
+  Header* hdr;
+  Slot* table;
+  uint64_t* bsum;
+  uint64_t* woff;
+  void* counts;
+  uint8_t* words;
+};
+
+bool tables_ok(const wc_result* const* t, uint32_t k) {
+  if (!t && k) return false;
+  for (uint32_t i = 0; i < k; ++i) {
+    if (!t[i]) return false;
+    if (t[i]->count_bytes != 4 && t[i]->count_bytes != 8) return false;
+    if (t[i]->n_entries && (!t[i]->d_word_offsets || !t[i]->d_counts || !t[i]->d_words))
+      return false;
+  }
+  return true;
+}
+
+void layout_merge(const wc_result* const* t, uint32_t k, const wc_opts* o, void* ws,
+                  MergeLayout* L) {
+  uint64_t n = 0, wb = 0;
+  for (uint32_t i = 0; i < k; ++i) {
+    n += t[i]->n_entries;
+    wb += t[i]->word_bytes;
+  }
+  uint64_t S = o && o->table_slots ? o->table_slots : next_pow2(std::max<uint64_t>(4096, 2 * n));
+  L->S = S;
+  L->n_blocks = (S + kExportSpan - 1) / kExportSpan;
+  L->word_cap = std::max<uint64_t>(o && o->word_bytes_cap ? o->word_bytes_cap : wb, 16);
+  uint32_t cb = o ? o->count_bytes : 8;
+  Bump B(ws);
+  L->hdr = B.take<Header>(sizeof(Header));
+  L->table = B.take<Slot>(S * sizeof(Slot));
+  L->bsum = B.take<uint64_t>(L->n_blocks * 16);
+  L->woff = B.take<uint64_t>((S + 1) * 8);
+  L->counts = B.take<uint8_t>(S * cb);
+  L->words = B.take<uint8_t>(L->word_cap);
+  L->total = B.off;
+}
+
+}  // namespace
+
+wc_status wc_merge_plan(const wc_result* const* tables, uint32_t k, const wc_opts* opts,
+                        wc_plan* out) {
+  if (!out || !tables_ok(tables, k)) return WC_EINVAL;
+  if (opts && (opts->count_bytes != 4 && opts->count_bytes != 8)) return WC_EINVAL;
+  if (opts && opts->table_slots && !is_pow2(opts->table_slots)) return WC_EINVAL;
+  MergeLayout L;
+  layout_merge(tables, k, opts, nullptr, &L);
+  out->table_slots = L.S;
+  out->workspace_bytes = L.total;
+  out->max_entries = L.S;
+  out->word_bytes_cap = L.word_cap;
+  return WC_OK;
+}
+
+wc_status wc_merge(const wc_result* const* tables, uint32_t k, const wc_opts* opts,
+                   void* d_workspace, uint64_t workspace_bytes, wc_result* out, void* stream) {
+  if (!out || !d_workspace || !tables_ok(tables, k)) return WC_EINVAL;
+  if (opts && (opts->count_bytes != 4 && opts->count_bytes != 8)) return WC_EINVAL;
+  if (opts && opts->table_slots && !is_pow2(opts->table_slots)) return WC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  MergeLayout L;
+  layout_merge(tables, k, opts, d_workspace, &L);
+  if (L.total > workspace_bytes) return WC_ENOMEM;
+  const uint32_t cb = opts ? opts->count_bytes : 8;
+  const uint64_t km = opts ? key_mask_of(opts) : ~0ull;
+  Timer tm;
+  HIPCHK(tm.init(opts && (opts->debug_flags & WC_DEBUG_TIME)));
+  if (tm.on) HIPCHK(hipEventRecord(tm.c, s));
+  HIPCHK(launch_fill_zero(L.hdr, sizeof(Header), s));
+  HIPCHK(launch_fill_zero(L.table, L.S * sizeof(Slot), s));
+  const uint64_t occ_limit = L.S - L.S / 8;
+  if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
+  for (uint32_t i = 0; i < k; ++i) {
+    MergeInput in;
+    in.word_offsets = tables[i]->d_word_offsets;
+    in.words = tables[i]->d_words;
+    in.counts = tables[i]->d_counts;
+    in.n = tables[i]->n_entries;
+    in.count_bytes = tables[i]->count_bytes;
+    in.column = 0;
+    HIPCHK(launch_merge_insert(in, L.table, L.S - 1, occ_limit, km, L.hdr, nullptr, 1, s));
+  }
+  if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
+  ExportParams E;
+  memset(&E, 0, sizeof(E));
+  E.table = L.table;
+  E.slots = L.S;
+  E.hdr = L.hdr;
+  E.block_sums = L.bsum;
+  E.n_blocks = L.n_blocks;
+  E.word_offsets = L.woff;
+  E.words = L.words;
+  E.word_cap = L.word_cap;
+  E.counts = L.counts;
+  E.count_bytes = cb;
+  HIPCHK(launch_export(E, s));
+  Header h;
+  HIPCHK(hipMemcpyAsync(&h, L.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  memset(out, 0, sizeof(*out));
+  out->n_entries = h.n_entries;
+  uint64_t total = 0;
+  out->word_bytes = h.word_bytes;
+  out->table_slots = L.S;
+  out->count_bytes = cb;
+  out->mode = WC_GLOBAL;
+  out->d_word_offsets = L.woff;
+  out->d_words = L.words;
+  out->d_counts = L.counts;
+  for (uint32_t i = 0; i < k; ++i) total += tables[i]->total_tokens;
+  out->total_tokens = total;
+  if (tm.on) {
+    HIPCHK(hipEventRecord(tm.d, s));
+    HIPCHK(hipEventSynchronize(tm.d));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, tm.a, tm.b));
+    out->kernel_ms = ms;
+    HIPCHK(hipEventElapsedTime(&ms, tm.c, tm.d));
+    out->total_ms = ms;
+  }
+  return finish_flags(h);
+}
+
+// ------------------------------------------------------------------------------------------
+// top-k distinctive words
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct TopkLayout {
+  uint64_t S, n_blocks, word_cap, row_word_cap, total;
+  uint32_t C, k;
+  Header* hdr;
+  Slot* table;
+  uint64_t* joint_slots;   // [S * C]
+  uint64_t* bsum;
+  uint64_t* woff;          // joint vocabulary
+  uint64_t* entry_total;   // [S] int64 counts of the joint table
+  uint8_t* words;
+  uint64_t* slot_of_entry;
+  uint64_t* joint_dense;   // [S * C]
+  uint64_t* totals;        // [64]
+  uint32_t* lists;
+  uint32_t* list_len;
+  uint64_t* out_entry;
+  uint64_t* n_rows;        // [64]
+  uint64_t* row_woff;
+  uint8_t* row_words;
+  uint64_t* row_nc;
+  uint64_t* row_nr;
+  double* row_score;
+};
+
+void layout_topk(const wc_result* const* t, uint32_t C, uint32_t k, void* ws, TopkLayout* L) {
+  uint64_t n = 0, wb = 0;
+  for (uint32_t i = 0; i < C; ++i) {
+    n += t[i]->n_entries;
+    wb += t[i]->word_bytes;
+  }
+  L->C = C;
+  L->k = k;
+  L->S = next_pow2(std::max<uint64_t>(4096, 2 * n));
+  L->n_blocks = (L->S + kExportSpan - 1) / kExportSpan;
+  L->word_cap = std::max<uint64_t>(wb, 16);
+  L->row_word_cap = std::max<uint64_t>(std::min<uint64_t>(wb, (uint64_t)C * wb), 16);
+  Bump B(ws);
+  L->hdr = B.take<Header>(sizeof(Header));
+  L->table = B.take<Slot>(L->S * sizeof(Slot));
+  L->joint_slots = B.take<uint64_t>(L->S * C * 8);
+  L->bsum = B.take<uint64_t>(L->n_blocks * 16);
+  L->woff = B.take<uint64_t>((L->S + 1) * 8);
+  L->entry_total = B.take<uint64_t>(L->S * 8);
+  L->words = B.take<uint8_t>(L->word_cap);
+  L->slot_of_entry = B.take<uint64_t>(L->S * 8);
+  L->joint_dense = B.take<uint64_t>(L->S * C * 8);
+  L->totals = B.take<uint64_t>(64 * 8);
+  L->lists = B.take<uint32_t>((uint64_t)C * 2 * kTopkThreads * k * 4);
+  L->list_len = B.take<uint32_t>((uint64_t)C * 2 * kTopkThreads * 4);
+  L->out_entry = B.take<uint64_t>((uint64_t)C * k * 8);
+  L->n_rows = B.take<uint64_t>(64 * 8);
+  L->row_woff = B.take<uint64_t>(((uint64_t)C * k + 1) * 8);
+  L->row_words = B.take<uint8_t>(L->row_word_cap * C);
+  L->row_nc = B.take<uint64_t>((uint64_t)C * k * 8);
+  L->row_nr = B.take<uint64_t>((uint64_t)C * k * 8);
+  L->row_score = B.take<double>((uint64_t)C * k * 8);
+  L->total = B.off;
+}
+
+__global__ void gather_joint_kernel(const uint64_t* joint_slots, const uint64_t* slot_of_entry,
+                                    const Header* hdr, uint32_t C, uint64_t* dense) {
+  uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (e >= hdr->n_entries) return;
+  uint64_t i = slot_of_entry[e];
+  for (uint32_t c = 0; c < C; ++c) dense[e * C + c] = joint_slots[i * C + c];
+}
+
+}  // namespace
+
+wc_status wc_topk_ratio_plan(const wc_result* const* corpora, uint32_t n_corpora, uint32_t k,
+                             uint64_t* workspace_bytes) {
+  if (!workspace_bytes || n_corpora == 0 || n_corpora > 64 || k == 0 || k > 4096)
+    return WC_EINVAL;
+  if (!tables_ok(corpora, n_corpora)) return WC_EINVAL;
+  TopkLayout L;
+  layout_topk(corpora, n_corpora, k, nullptr, &L);
+  *workspace_bytes = L.total;
+  return WC_OK;
+}
+
+wc_status wc_topk_ratio(const wc_result* const* corpora, uint32_t n_corpora, uint32_t k,
+                        uint64_t min_count, void* d_workspace, uint64_t workspace_bytes,
+                        wc_topk* out, void* stream) {
+  if (!out || !d_workspace || n_corpora == 0 || n_corpora > 64 || k == 0 || k > 4096)
+    return WC_EINVAL;
+  if (!tables_ok(corpora, n_corpora)) return WC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  TopkLayout L;
+  layout_topk(corpora, n_corpora, k, d_workspace, &L);
+  if (L.total > workspace_bytes) return WC_ENOMEM;
+  const uint32_t C = n_corpora;
+  HIPCHK(launch_fill_zero(L.hdr, sizeof(Header), s));
+  HIPCHK(launch_fill_zero(L.table, L.S * sizeof(Slot), s));
+  HIPCHK(launch_fill_zero(L.joint_slots, L.S * C * 8, s));
+  HIPCHK(launch_fill_zero(L.totals, 64 * 8, s));
+  const uint64_t occ_limit = L.S - L.S / 8;
+  for (uint32_t c = 0; c < C; ++c) {
+    MergeInput in;
+    in.word_offsets = corpora[c]->d_word_offsets;
+    in.words = corpora[c]->d_words;
+    in.counts = corpora[c]->d_counts;
+    in.n = corpora[c]->n_entries;
+    in.count_bytes = corpora[c]->count_bytes;
+    in.column = c;
+    HIPCHK(launch_merge_insert(in, L.table, L.S - 1, occ_limit, ~0ull, L.hdr, L.joint_slots, C, s));
+  }
+  ExportParams E;
+  memset(&E, 0, sizeof(E));
+  E.table = L.table;
+  E.slots = L.S;
+  E.hdr = L.hdr;
+  E.block_sums = L.bsum;
+  E.n_blocks = L.n_blocks;
+  E.word_offsets = L.woff;
+  E.words = L.words;
+  E.word_cap = L.word_cap;
+  E.counts = L.entry_total;
+  E.count_bytes = 8;
+  E.slot_of_entry = L.slot_of_entry;
+  HIPCHK(launch_export(E, s));
+  uint32_t grid = (uint32_t)((L.S + 255) / 256);
+  hipLaunchKernelGGL(gather_joint_kernel, dim3(grid), dim3(256), 0, s, L.joint_slots,
+                     L.slot_of_entry, L.hdr, C, L.joint_dense);
+  HIPCHK(hipGetLastError());
+  Header h;
+  HIPCHK(hipMemcpyAsync(&h, L.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h.flags) return finish_flags(h);
+  TopkParams P;
+  P.word_offsets = L.woff;
+  P.words = L.words;
+  P.joint = L.joint_dense;
+  P.V = h.n_entries;
+  P.C = C;
+  P.k = k;
+  P.min_count = min_count;
+  P.totals = L.totals;
+  P.lists = L.lists;
+  P.list_len = L.list_len;
+  P.out_entry = L.out_entry;
+  P.n_rows = L.n_rows;
+  P.out_word_offsets = L.row_woff;
+  P.out_words = L.row_words;
+  P.out_nc = L.row_nc;
+  P.out_nr = L.row_nr;
+  P.out_score = L.row_score;
+  P.entry_total = L.entry_total;
+  HIPCHK(launch_topk(P, s));
+  memset(out, 0, sizeof(*out));
+  HIPCHK(hipMemcpyAsync(out->n_rows, L.n_rows, 8 * C, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&out->word_bytes, L.row_woff + (uint64_t)C * k, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out->n_corpora = C;
+  out->k = k;
+  out->vocab_size = h.n_entries;
+  out->d_word_offsets = L.row_woff;
+  out->d_words = L.row_words;
+  out->d_n_c = L.row_nc;
+  out->d_n_rest = L.row_nr;
+  out->d_score = L.row_score;
+  return WC_OK;
+}
+
+wc_status wc_hash_words(const uint8_t* d_bytes, const uint64_t* d_offsets, uint64_t n,
+                        uint64_t* d_out, void* stream) {
+  if (n && (!d_bytes || !d_offsets || !d_out)) return WC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(launch_hash_words(d_bytes, d_offsets, n, d_out, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return WC_OK;
+}
+
+}  // extern "C"

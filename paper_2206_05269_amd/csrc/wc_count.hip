@@ -1,0 +1,521 @@
+// Count kernel: the map (tokenise, hash) and the first level of the reduce (merge counts),
+// fused. Section 3.1 counts each document's words in its own dictionary on CPU threads and
+// Section 3.3 sums the grouped counts on the GPU; here one kernel scans the raw bytes, keeps
+// a per-workgroup dictionary in LDS and merges it into one table in device memory, which is
+// the GPU-resident dictionary that Section 5.2 proposes.
+//
+// Work split. The corpus is cut into stages of BLOCK*16 bytes at 16-byte aligned addresses;
+// each workgroup scans a contiguous run of stages, 16 bytes per thread per stage (one
+// 128-bit load), with the next stage's load in flight while the current one is processed.
+// A word belongs to the stage holding its first byte; its owner reads past the stage end
+// when the word continues (the result does not depend on where stages or workgroups cut).
+//
+// Per stage:
+//   1. fold + classify 16 bytes per thread (SWAR), store folded bytes to LDS;
+//   2. mark document starts that fall in the stage (from a precomputed per-stage cursor);
+//   3. word-start / word-last bit masks from the byte classes of the thread and its
+//      neighbours; block prefix sum of start counts compacts the starts into a list;
+//   4. each thread takes tokens from the list: its length comes from the next word-last bit;
+//      a word of <= 16 bytes is packed from LDS and counted in the LDS table; a longer word,
+//      or one that runs past the stage, is read from device memory, hashed with FNV-1a 64
+//      and inserted straight into the global table;
+//   5. when the LDS table passes its load limit it is flushed: every entry is hashed with
+//      FNV-1a 64 and added to the global table with one atomic add.
+#include "wc_internal.h"
+
+namespace wc {
+
+struct LdsTable {
+  uint64_t* lo;     // claim word: packed bytes 0..7 (0 = empty)
+  uint64_t* hi;     // packed bytes 8..15 | kTop (0 until published)
+  uint32_t* cnt;
+  uint32_t* doc1;   // per-document mode: document + 1 (0 until published)
+  uint32_t mask;
+  uint32_t shift;   // 32 - log2(entries)
+};
+
+WC_DEV uint32_t lds_hash(uint64_t lo, uint64_t hi, uint32_t doc1) {
+  uint32_t a = (uint32_t)lo, b = (uint32_t)(lo >> 32), c = (uint32_t)hi, d = (uint32_t)(hi >> 32);
+  uint32_t h = a * 0x9E3779B1u ^ (b * 0x85EBCA77u) ^ (c * 0xC2B2AE3Du) ^ (d * 0x27D4EB2Fu) ^
+               (doc1 * 0x165667B1u);
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 13;
+  return h;
+}
+
+WC_DEV uint64_t lds_ld64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+WC_DEV uint32_t lds_ld32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Count one occurrence of a short word in the LDS table. Returns false when no slot was
+// found within kMaxProbe probes (the caller then counts it in the global table).
+//
+// The probe loop is wave-uniform: it runs while any active lane of the wave still has work,
+// so a lane that claims a slot publishes its identity inside the same iteration, before any
+// lane of the wave reads it; a lane that finds a claimed but unpublished slot looks at it
+// again in the next iteration instead of waiting. No lane ever waits on another lane.
+template <bool kPerDoc>
+WC_DEV bool lds_insert(const LdsTable& L, uint64_t lo, uint64_t hi, uint32_t doc1,
+                       uint32_t* used) {
+  constexpr int kMaxProbe = 32;
+  const uint64_t hiw = hi | kTop;
+  uint32_t i = lds_hash(lo, hi, doc1) >> L.shift;
+  int probe = 0;
+  bool active = true, ok = false;
+  while (__any(active)) {
+    uint64_t old = 1;
+    if (active) old = atomicCAS((unsigned long long*)&L.lo[i], 0ull, (unsigned long long)lo);
+    const bool won = active && old == 0;
+    if (won) {
+      if (kPerDoc) __hip_atomic_store(&L.doc1[i], doc1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_store(&L.hi[i], hiw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      atomicAdd(&L.cnt[i], 1u);
+      atomicAdd(used, 1u);
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // publication above stays before the reads below
+    if (active) {
+      bool advance = true;
+      if (won) {
+        ok = true;
+        active = false;
+        advance = false;
+      } else if (old == lo) {
+        uint64_t sh = lds_ld64(&L.hi[i]);
+        uint32_t sd = kPerDoc ? lds_ld32(&L.doc1[i]) : 1u;
+        if (sh == 0 || sd == 0) {
+          advance = false;  // claimed, not yet published: look again next iteration
+        } else if (sh == hiw && (!kPerDoc || sd == doc1)) {
+          atomicAdd(&L.cnt[i], 1u);
+          ok = true;
+          active = false;
+          advance = false;
+        }
+      }
+      if (advance) {
+        i = (i + 1) & L.mask;
+        if (++probe >= kMaxProbe) active = false;
+      }
+    }
+  }
+  return ok;
+}
+
+template <bool kPerDoc>
+WC_DEV uint64_t short_key(uint64_t lo, uint64_t hi, uint32_t doc1, uint64_t key_mask) {
+  uint64_t h = fnv_packed(lo, hi, packed_len(lo, hi));
+  if (kPerDoc) h = fnv_u32(h, doc1 - 1);
+  return finish_key(h, key_mask);
+}
+
+// Scan a word from logical position s (its first byte) in device memory, up to `limit`
+// (exclusive; the document end) or the first non-word byte. Returns the length, the packed
+// bytes when the length is <= 16, and the FNV-1a 64 hash of the folded bytes.
+WC_DEV uint64_t scan_word(const uint8_t* corpus, uint64_t s, uint64_t limit, uint64_t* plo,
+                          uint64_t* phi, uint64_t* pfnv) {
+  uint64_t h = kFnvOffset, lo = 0, hi = 0, n = 0;
+  uint64_t p = s;
+  bool done = false;
+  while (!done && p < limit) {
+    // the aligned 16-byte block containing p, when it lies inside [corpus, corpus + limit);
+    // otherwise single bytes (limit <= corpus length, so no byte past the buffer is read)
+    uintptr_t a = ((uintptr_t)(corpus + p)) & ~(uintptr_t)15;
+    uint32_t first = (uint32_t)((uintptr_t)(corpus + p) - a);
+    uint32_t wds[4];
+    bool vec = a >= (uintptr_t)corpus && a + 16 <= (uintptr_t)(corpus + limit);
+    if (vec) {
+      uint4 v = *(const uint4*)a;
+      wds[0] = v.x; wds[1] = v.y; wds[2] = v.z; wds[3] = v.w;
+    }
+    for (uint32_t j = first; j < 16; ++j) {
+      if (p >= limit) { done = true; break; }
+      uint32_t b = vec ? (wds[j >> 2] >> ((j & 3) * 8)) & 0xffu : (uint32_t)corpus[p];
+      if (!is_word_byte(b)) { done = true; break; }
+      uint32_t f = fold_byte(b);
+      h = fnv_step(h, f);
+      if (n < 8) lo |= (uint64_t)f << (8 * n);
+      else if (n < 16) hi |= (uint64_t)f << (8 * (n - 8));
+      ++n;
+      ++p;
+    }
+  }
+  *plo = lo;
+  *phi = hi;
+  *pfnv = h;
+  return n;
+}
+
+template <int BLOCK, bool kPerDoc>
+__global__ __launch_bounds__(BLOCK) void count_kernel(CountParams P) {
+  constexpr int STAGE = BLOCK * 16;
+  constexpr int NWAVE = BLOCK / 64;
+  constexpr int MAXB = 256;  // document starts kept per stage for per-document lookups
+  __shared__ uint4 s_txt4[STAGE / 16 + 2];        // folded bytes of the stage (+32 B pad)
+  __shared__ uint16_t s_wm[BLOCK];                // word-byte mask per thread
+  __shared__ uint16_t s_last[BLOCK + 1];          // word-last mask per thread
+  __shared__ uint32_t s_bnd[STAGE / 32 + 2];      // document start at byte i (0..STAGE)
+  __shared__ uint16_t s_starts[STAGE];            // compacted token starts
+  __shared__ uint32_t s_wsum[NWAVE];
+  __shared__ uint16_t s_boff[kPerDoc ? MAXB : 1]; // stage-relative document starts
+  __shared__ uint32_t s_used;
+  __shared__ uint32_t s_carry[2];                 // word-byte flag of the previous stage's last byte
+  __shared__ uint32_t s_next_w;                   // word-byte flag of the next stage's first byte
+  __shared__ uint32_t s_ntok;
+  extern __shared__ __align__(16) uint8_t s_dyn[];
+  const uint8_t* s_txt = (const uint8_t*)s_txt4;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  Header* hdr = P.hdr;
+
+  if (ld_relaxed32(&hdr->flags) & kFlagBadOffsets) return;
+
+  LdsTable L;
+  const uint32_t E = P.lds_entries;
+  L.lo = (uint64_t*)s_dyn;
+  L.hi = L.lo + E;
+  L.cnt = (uint32_t*)(L.hi + E);
+  L.doc1 = L.cnt + E;
+  L.mask = E - 1;
+  L.shift = 32 - (31 - __clz(E));
+  const bool use_lds = !P.no_lds;
+
+  for (uint32_t i = tid; i < E; i += BLOCK) {
+    L.lo[i] = 0;
+    L.hi[i] = 0;
+    L.cnt[i] = 0;
+    if (kPerDoc) L.doc1[i] = 0;
+  }
+  if (tid == 0) s_used = 0;
+
+  const uint64_t st0 = (uint64_t)blockIdx.x * P.stages_per_wg;
+  const uint64_t st1 = min(st0 + P.stages_per_wg, P.n_stages);
+  if (st0 >= st1) return;
+
+  const int64_t R0 = (int64_t)P.offsets[0], R1 = (int64_t)P.offsets[P.n_docs];
+  const int64_t len = (int64_t)P.len;
+
+  // logical position of byte j of thread t in stage k
+  auto stage_pos = [&](uint64_t k) -> int64_t { return P.base_off + (int64_t)(k * STAGE); };
+
+  auto load16 = [&](uint64_t k) -> uint4 {
+    int64_t p = stage_pos(k) + tid * 16;
+    uint4 v;
+    if (p >= 0 && p + 16 <= len) {
+      v = *(const uint4*)(P.corpus + p);
+    } else {
+      uint32_t w[4] = {0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u};
+      for (int j = 0; j < 16; ++j) {
+        int64_t q = p + j;
+        if (q >= 0 && q < len) {
+          uint32_t b = P.corpus[q];
+          w[j >> 2] = (w[j >> 2] & ~(0xffu << ((j & 3) * 8))) | (b << ((j & 3) * 8));
+        }
+      }
+      v = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    return v;
+  };
+
+  // word-byte flag of the byte at logical position q (0 outside the document range)
+  auto wflag_at = [&](int64_t q) -> uint32_t {
+    if (q < R0 || q >= R1 || q < 0 || q >= len) return 0u;
+    return is_word_byte(P.corpus[q]) ? 1u : 0u;
+  };
+
+  if (tid == 0) s_carry[(st0 & 1) ^ 1] = wflag_at(stage_pos(st0) - 1);
+  for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
+
+  uint4 cur = load16(st0);
+  uint64_t tokens = 0;
+
+  for (uint64_t k = st0; k < st1; ++k) {
+    const int64_t ls = stage_pos(k);
+    const int64_t le = ls + STAGE;
+    uint4 nxt = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
+    if (k + 1 < st1) nxt = load16(k + 1);
+
+    // ---- 1. fold + classify --------------------------------------------------------
+    uint32_t f0, f1, f2, f3;
+    uint32_t g0 = fold_classify4(cur.x, &f0), g1 = fold_classify4(cur.y, &f1);
+    uint32_t g2 = fold_classify4(cur.z, &f2), g3 = fold_classify4(cur.w, &f3);
+    uint32_t w16 = movemask4(f0) | (movemask4(f1) << 4) | (movemask4(f2) << 8) |
+                   (movemask4(f3) << 12);
+    const int64_t p = ls + tid * 16;
+    if (p < R0 || p + 16 > R1) {
+      int64_t lo_cut = R0 - p, hi_cut = R1 - p;
+      uint32_t m = 0xffffu;
+      if (lo_cut > 0) m &= lo_cut >= 16 ? 0u : (0xffffu << lo_cut) & 0xffffu;
+      if (hi_cut < 16) m &= hi_cut <= 0 ? 0u : (0xffffu >> (16 - hi_cut));
+      w16 &= m;
+    }
+    s_txt4[tid] = make_uint4(g0, g1, g2, g3);
+    s_wm[tid] = (uint16_t)w16;
+    if (tid == 0) {
+      // flag of the first byte of the next stage
+      int64_t q = le;
+      uint32_t nw;
+      if (k + 1 < st1) {
+        nw = (q >= R0 && q < R1 && q < len) ? (is_word_byte(nxt.x & 0xffu) ? 1u : 0u) : 0u;
+      } else {
+        nw = wflag_at(q);
+      }
+      s_next_w = nw;
+    }
+
+    // ---- 2. document starts in [ls, le] ----------------------------------------------
+    const uint64_t c0 = P.stage_doc[k];       // first document start >= ls
+    const uint64_t c1 = P.stage_doc[k + 1];   // first document start >= le
+    const uint64_t nb = c1 - c0;
+    for (uint64_t j = tid; j < nb; j += BLOCK) {
+      uint64_t rel = P.offsets[c0 + j] - (uint64_t)ls;
+      atomicOr(&s_bnd[rel >> 5], 1u << (rel & 31));
+      if (kPerDoc && j < MAXB) s_boff[j] = (uint16_t)rel;
+    }
+    if (tid == 0 && c1 <= P.n_docs && (int64_t)P.offsets[c1] == le)
+      atomicOr(&s_bnd[STAGE >> 5], 1u);
+    __syncthreads();
+
+    // ---- 3. start / last masks, compaction --------------------------------------------
+    uint32_t prev = tid > 0 ? (s_wm[tid - 1] >> 15) : s_carry[(k & 1) ^ 1];
+    uint32_t next = tid < BLOCK - 1 ? (s_wm[tid + 1] & 1u) : s_next_w;
+    uint32_t bnd = (s_bnd[tid >> 1] >> ((tid & 1) * 16)) & 0xffffu;
+    uint32_t bnext = (s_bnd[(tid + 1) >> 1] >> (((tid + 1) & 1) * 16)) & 1u;
+    uint32_t wprev = ((w16 << 1) | prev) & 0xffffu;
+    uint32_t start16 = w16 & (~wprev | bnd);
+    uint32_t wnext = (w16 >> 1) | (next << 15);
+    uint32_t bn16 = (bnd >> 1) | (bnext << 15);
+    uint32_t last16 = w16 & (~wnext | bn16) & 0xffffu;
+    s_last[tid] = (uint16_t)last16;
+    if (tid == BLOCK - 1) {
+      s_carry[k & 1] = w16 >> 15;
+      s_last[BLOCK] = 0;
+    }
+
+    uint32_t cnt = __popc(start16);
+    uint32_t incl = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+    for (int w = 0; w < NWAVE; ++w) {
+      uint32_t v = s_wsum[w];
+      base += w < wave ? v : 0u;
+      total += v;
+    }
+    uint32_t o = base + incl - cnt;
+    uint32_t m = start16;
+    while (m) {
+      int j = __ffs(m) - 1;
+      s_starts[o++] = (uint16_t)(tid * 16 + j);
+      m &= m - 1;
+    }
+    tokens += (tid == 0) ? total : 0u;
+    __syncthreads();
+    // the boundary bitmap has been read (step 3): clear it for the next stage
+    for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
+
+    // ---- 4. tokens -------------------------------------------------------------------
+    for (uint32_t t = tid; t < total; t += BLOCK) {
+      const uint32_t s = s_starts[t];
+      // next word-last bit at or after s
+      uint32_t q = s >> 4;
+      uint32_t bits = (uint32_t)s_last[q] >> (s & 15);
+      uint32_t e;
+      bool crosses = false;
+      if (bits) {
+        e = s + __ffs(bits) - 1;
+      } else {
+        ++q;
+        while (q < BLOCK && s_last[q] == 0) ++q;
+        if (q < BLOCK) e = q * 16 + __ffs(s_last[q]) - 1;
+        else { crosses = true; e = STAGE - 1; }
+      }
+      uint32_t doc1 = 0;
+      if (kPerDoc) {
+        // document of position ls + s: (first start > ls + s) - 1
+        uint64_t cnt_le;
+        if (nb <= MAXB) {
+          uint32_t lo_i = 0, hi_i = (uint32_t)nb;
+          while (lo_i < hi_i) {
+            uint32_t mid = (lo_i + hi_i) >> 1;
+            if (s_boff[mid] <= s) lo_i = mid + 1; else hi_i = mid;
+          }
+          cnt_le = lo_i;
+        } else {
+          uint64_t lo_i = 0, hi_i = nb;
+          while (lo_i < hi_i) {
+            uint64_t mid = (lo_i + hi_i) >> 1;
+            if (P.offsets[c0 + mid] <= (uint64_t)(ls + s)) lo_i = mid + 1; else hi_i = mid;
+          }
+          cnt_le = lo_i;
+        }
+        doc1 = (uint32_t)(c0 + cnt_le);  // (doc index) + 1
+      }
+      const uint32_t wl = e - s + 1;
+      if (!crosses && wl <= 16) {
+        // pack from LDS: 20 bytes starting at the aligned dword of s
+        const uint32_t* tw = (const uint32_t*)s_txt;
+        uint32_t di = s >> 2, sh = s & 3;
+        uint32_t d0 = tw[di], d1 = tw[di + 1], d2 = tw[di + 2], d3 = tw[di + 3], d4 = tw[di + 4];
+        uint32_t k0 = __builtin_amdgcn_alignbyte(d1, d0, sh);
+        uint32_t k1 = __builtin_amdgcn_alignbyte(d2, d1, sh);
+        uint32_t k2 = __builtin_amdgcn_alignbyte(d3, d2, sh);
+        uint32_t k3 = __builtin_amdgcn_alignbyte(d4, d3, sh);
+        uint64_t lo = (uint64_t)k0 | ((uint64_t)k1 << 32);
+        uint64_t hi = (uint64_t)k2 | ((uint64_t)k3 << 32);
+        if (wl < 8) { lo &= (1ull << (8 * wl)) - 1; hi = 0; }
+        else if (wl == 8) { hi = 0; }
+        else if (wl < 16) { hi &= (1ull << (8 * (wl - 8))) - 1; }
+        bool done = use_lds && lds_insert<kPerDoc>(L, lo, hi, doc1, &s_used);
+        if (!done) {
+          uint64_t key = short_key<kPerDoc>(lo, hi, doc1, P.key_mask);
+          table_insert<kPerDoc>(P.table, P.mask, key, short_id(lo, hi, doc1), 1, hdr, P.occ_limit);
+        }
+      } else {
+        // long word, or a word that continues past the stage: read it from device memory
+        uint64_t start = (uint64_t)(ls + s);
+        uint64_t limit = (uint64_t)R1;
+        if (crosses) {
+          uint64_t nd = P.offsets[c1 <= P.n_docs ? c1 : P.n_docs];
+          if (nd > (uint64_t)le && nd < limit) limit = nd;
+        } else {
+          limit = start + wl;
+        }
+        uint64_t lo, hi, h;
+        uint64_t n = scan_word(P.corpus, start, limit, &lo, &hi, &h);
+        if (n <= 16) {
+          bool done = use_lds && lds_insert<kPerDoc>(L, lo, hi, doc1, &s_used);
+          if (!done) {
+            uint64_t key = short_key<kPerDoc>(lo, hi, doc1, P.key_mask);
+            table_insert<kPerDoc>(P.table, P.mask, key, short_id(lo, hi, doc1), 1, hdr, P.occ_limit);
+          }
+        } else {
+          if (kPerDoc) h = fnv_u32(h, doc1 - 1);
+          uint64_t key = finish_key(h, P.key_mask);
+          table_insert<kPerDoc>(P.table, P.mask, key, long_id(P.corpus + start, n, doc1), 1, hdr,
+                                P.occ_limit);
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- 5. flush ---------------------------------------------------------------------
+    const bool last_stage = (k + 1 == st1);
+    if (use_lds && (last_stage || (P.policy == WC_FLUSH_ALL && s_used > P.lds_flush_at))) {
+      for (uint32_t i = tid; i < E; i += BLOCK) {
+        uint32_t c = L.cnt[i];
+        if (c) {
+          uint64_t lo = L.lo[i], hi = L.hi[i] & ~kTop;
+          uint32_t d1 = kPerDoc ? L.doc1[i] : 0u;
+          uint64_t key = short_key<kPerDoc>(lo, hi, d1, P.key_mask);
+          table_insert<kPerDoc>(P.table, P.mask, key, short_id(lo, hi, d1), c, hdr, P.occ_limit);
+          L.cnt[i] = 0;
+        }
+        L.lo[i] = 0;
+        L.hi[i] = 0;
+        if (kPerDoc) L.doc1[i] = 0;
+      }
+      __syncthreads();
+      if (tid == 0) s_used = 0;
+      __syncthreads();
+    }
+    cur = nxt;
+  }
+  if (tid == 0) add64(&hdr->total_tokens, tokens);
+}
+
+// First document start at or after the start of each stage (one binary search per stage).
+__global__ void stage_doc_kernel(const uint64_t* __restrict__ offsets, uint64_t n_docs,
+                                 int64_t base_off, uint32_t stage, uint64_t n_stages,
+                                 uint64_t* __restrict__ out) {
+  uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (k > n_stages) return;
+  int64_t ls = base_off + (int64_t)(k * stage);
+  uint64_t lo = 0, hi = n_docs + 1;  // search offsets[0..n_docs]
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if ((int64_t)offsets[mid] < ls) lo = mid + 1; else hi = mid;
+  }
+  out[k] = lo;
+}
+
+// Offsets must be non-decreasing and end inside the corpus.
+__global__ void validate_offsets_kernel(const uint64_t* __restrict__ offsets, uint64_t n_docs,
+                                        uint64_t len, Header* hdr) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i > n_docs) return;
+  bool bad = false;
+  if (i < n_docs && offsets[i] > offsets[i + 1]) bad = true;
+  if (i == n_docs && offsets[i] > len) bad = true;
+  if (bad) or32(&hdr->flags, kFlagBadOffsets);
+}
+
+__global__ void read_range_kernel(const uint64_t* offsets, uint64_t n_docs, uint64_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = offsets[0];
+    out[1] = offsets[n_docs];
+  }
+}
+
+template <bool kPerDoc>
+static hipError_t launch_count_t(const CountParams& P, uint32_t grid, uint32_t block,
+                                 size_t dyn, hipStream_t s) {
+  if (block == 512) {
+    hipLaunchKernelGGL((count_kernel<512, kPerDoc>), dim3(grid), dim3(512), dyn, s, P);
+  } else {
+    hipLaunchKernelGGL((count_kernel<256, kPerDoc>), dim3(grid), dim3(256), dyn, s, P);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const CountParams& P, bool per_doc, uint32_t grid, uint32_t block,
+                        size_t dyn, hipStream_t s) {
+  return per_doc ? launch_count_t<true>(P, grid, block, dyn, s)
+                 : launch_count_t<false>(P, grid, block, dyn, s);
+}
+
+hipError_t set_count_smem(uint32_t block, size_t dyn) {
+  hipError_t e = hipSuccess;
+  if (block == 512) {
+    e = hipFuncSetAttribute((const void*)count_kernel<512, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)count_kernel<512, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+  } else {
+    e = hipFuncSetAttribute((const void*)count_kernel<256, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)count_kernel<256, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+  }
+  return e;
+}
+
+hipError_t launch_stage_doc(const uint64_t* offsets, uint64_t n_docs, int64_t base_off,
+                            uint32_t stage, uint64_t n_stages, uint64_t* out, hipStream_t s) {
+  uint64_t n = n_stages + 1;
+  uint32_t grid = (uint32_t)((n + 255) / 256);
+  hipLaunchKernelGGL(stage_doc_kernel, dim3(grid), dim3(256), 0, s, offsets, n_docs, base_off,
+                     stage, n_stages, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const uint64_t* offsets, uint64_t n_docs, uint64_t len, Header* hdr,
+                           hipStream_t s) {
+  uint64_t n = n_docs + 1;
+  uint32_t grid = (uint32_t)((n + 255) / 256);
+  hipLaunchKernelGGL(validate_offsets_kernel, dim3(grid), dim3(256), 0, s, offsets, n_docs, len,
+                     hdr);
+  return hipGetLastError();
+}
+
+}  // namespace wc

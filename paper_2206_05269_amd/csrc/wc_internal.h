@@ -1,0 +1,124 @@
+// Internal interfaces between the host API (wc_api.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wc.h"
+#include "wc_device.h"
+
+namespace wc {
+
+struct CountParams {
+  const uint8_t* corpus;     // logical byte 0
+  uint64_t len;
+  const uint64_t* offsets;   // [n_docs + 1]
+  uint64_t n_docs;
+  uint64_t R0, R1;           // offsets[0], offsets[n_docs] (host copies)
+  Slot* table;
+  uint64_t mask;             // slots - 1
+  uint64_t occ_limit;        // claimed slots above this set the full flag
+  uint64_t key_mask;
+  Header* hdr;
+  const uint64_t* stage_doc; // [n_stages + 1]
+  int64_t base_off;          // logical position of stage 0 (<= 0, > -16)
+  uint64_t n_stages;
+  uint64_t stages_per_wg;
+  uint32_t lds_entries;
+  uint32_t lds_flush_at;
+  uint32_t policy;
+  uint32_t no_lds;
+};
+
+hipError_t launch_count(const CountParams& P, bool per_doc, uint32_t grid, uint32_t block,
+                        size_t dyn, hipStream_t s);
+hipError_t set_count_smem(uint32_t block, size_t dyn);
+hipError_t launch_stage_doc(const uint64_t* offsets, uint64_t n_docs, int64_t base_off,
+                            uint32_t stage, uint64_t n_stages, uint64_t* out, hipStream_t s);
+hipError_t launch_validate(const uint64_t* offsets, uint64_t n_docs, uint64_t len, Header* hdr,
+                           hipStream_t s);
+
+// ---- export (compaction of a table into dense arrays) -----------------------------------
+struct ExportParams {
+  const Slot* table;
+  uint64_t slots;
+  Header* hdr;
+  uint64_t* block_sums;      // [2 * n_blocks] (entries, bytes) per block, then scanned
+  uint64_t n_blocks;
+  uint64_t* word_offsets;    // [slots + 1]
+  uint8_t* words;
+  uint64_t word_cap;
+  void* counts;
+  uint32_t count_bytes;
+  uint32_t per_doc;
+  uint64_t* docs;            // per-document: entry document
+  uint64_t* slot_of_entry;   // optional: entry -> slot (joint tables)
+  uint64_t* entry_of_slot;   // optional: slot -> entry
+};
+constexpr uint32_t kExportBlock = 256;
+constexpr uint32_t kExportItems = 4;  // slots per thread
+constexpr uint64_t kExportSpan = kExportBlock * kExportItems;
+
+hipError_t launch_export(const ExportParams& E, hipStream_t s);
+hipError_t launch_export_list(const ExportParams& E, hipStream_t s);
+hipError_t launch_slot_lens(const Slot* table, const uint64_t* slots, uint64_t n, uint64_t* lens,
+                            hipStream_t s);
+hipError_t launch_slot_write(const Slot* table, const uint64_t* slots, uint64_t n,
+                             const uint64_t* word_offsets, uint8_t* words, void* counts,
+                             uint32_t count_bytes, uint64_t* docs, Header* hdr, hipStream_t s);
+hipError_t sort_pairs_u64(void* temp, size_t* temp_bytes, const uint64_t* keys_in,
+                          uint64_t* keys_out, const uint64_t* vals_in, uint64_t* vals_out,
+                          uint64_t n, int end_bit, hipStream_t s);
+hipError_t excl_sum_u64(void* temp, size_t* temp_bytes, const uint64_t* in, uint64_t* out,
+                        uint64_t n, hipStream_t s);
+
+// per-document CSR: sort entries by document
+hipError_t launch_doc_csr(const uint64_t* docs_in, uint64_t n_entries_max, const Header* hdr,
+                          uint64_t n_docs, uint64_t* doc_ptr, hipStream_t s);
+
+// ---- fills ---------------------------------------------------------------------------------
+hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t s);
+
+// ---- merge ---------------------------------------------------------------------------------
+struct MergeInput {
+  const uint64_t* word_offsets;
+  const uint8_t* words;
+  const void* counts;
+  uint64_t n;
+  uint32_t count_bytes;
+  uint32_t column;           // joint tables: column of this input
+};
+hipError_t launch_merge_insert(const MergeInput& in, Slot* table, uint64_t mask,
+                               uint64_t occ_limit, uint64_t key_mask, Header* hdr,
+                               uint64_t* joint_counts, uint32_t n_columns, hipStream_t s);
+
+// ---- top-k ---------------------------------------------------------------------------------
+struct TopkParams {
+  const uint64_t* word_offsets;  // joint vocabulary, V entries
+  const uint8_t* words;
+  const uint64_t* joint;         // [V * C] counts, entry-major
+  uint64_t V;
+  uint32_t C;
+  uint32_t k;
+  uint64_t min_count;
+  uint64_t* totals;              // [C] token totals per corpus (computed by a kernel)
+  uint32_t* lists;               // scratch: [C][2][T][k] entry indices
+  uint32_t* list_len;            // scratch: [C][2][T]
+  uint64_t* out_entry;           // [C * k] selected entries
+  uint64_t* n_rows;              // [C]
+  // outputs
+  uint64_t* out_word_offsets;    // [C*k + 1]
+  uint8_t* out_words;
+  uint64_t* out_nc;
+  uint64_t* out_nr;
+  double* out_score;
+  const uint64_t* entry_total;   // [V] sum over corpora
+};
+constexpr uint32_t kTopkThreads = 256;
+hipError_t launch_topk(const TopkParams& P, hipStream_t s);
+
+// ---- hashing (debug entry point) ------------------------------------------------------------
+hipError_t launch_hash_words(const uint8_t* bytes, const uint64_t* offsets, uint64_t n,
+                             uint64_t* out, hipStream_t s);
+
+}  // namespace wc

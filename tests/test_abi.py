@@ -1,0 +1,67 @@
+"""The C ABI without a GPU: libwc.so loads, exports every function include/wc.h declares, and
+the ctypes structures of the binding have the C layout (checked with a small gcc program)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2206_05269_amd import wc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wc.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*[\w\s\*]+?\b(wc_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    f = declared_functions()
+    for name in ("wc_count", "wc_count_plan", "wc_merge", "wc_merge_plan", "wc_topk_ratio",
+                 "wc_topk_ratio_plan", "wc_strerror", "wc_last_hip_error", "wc_hash_words"):
+        assert name in f
+
+
+def test_library_exports_every_declared_symbol():
+    L = wc.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_strerror_without_gpu():
+    L = wc.lib()
+    assert L.wc_strerror(0) == b"ok"
+    assert b"table" in L.wc_strerror(-3)
+
+
+def test_plan_without_gpu():
+    p = wc.count_plan(8 << 30, 1, count_bytes=8, table_slots=1 << 22)
+    assert p.table_slots == 1 << 22 and p.workspace_bytes > (1 << 22) * 32
+    with pytest.raises(wc.WcError):
+        wc.count_plan(100, 1, count_bytes=3)
+    with pytest.raises(wc.WcError):
+        wc.count_plan(100, 1, table_slots=1000)
+
+
+def test_struct_layouts_match_c(tmp_path):
+    prog = tmp_path / "sizes.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "wc.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(wc_tuning),"
+        " sizeof(wc_opts), sizeof(wc_plan), sizeof(wc_result), sizeof(wc_topk),"
+        " offsetof(wc_result, d_word_offsets), offsetof(wc_result, kernel_ms),"
+        " offsetof(wc_topk, n_rows));return 0;}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o",
+                    str(exe)], check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True,
+                                       check=True).stdout.split()))
+    want = [ctypes.sizeof(wc.Tuning), ctypes.sizeof(wc.Opts), ctypes.sizeof(wc.Plan),
+            ctypes.sizeof(wc.Result), ctypes.sizeof(wc.TopKStruct),
+            wc.Result.d_word_offsets.offset, wc.Result.kernel_ms.offset,
+            wc.TopKStruct.n_rows.offset]
+    assert got == want

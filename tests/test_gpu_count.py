@@ -1,0 +1,354 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit for bit.
+
+Counts are integers, so the bar is exact equality of the (word, count) tables and of the token
+totals. Inputs cover the paper's examples, brute-force alphabets, ragged stage and chunk
+boundaries, misaligned buffers, long words, forced hash collisions, a table that must grow,
+every tuning point, and the synthetic workloads (full size where the oracle's answer is known
+from the generator's rank histogram).
+"""
+import collections
+import itertools
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2206_05269_amd import synth
+from paper_2206_05269_amd import wc
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(text: bytes | np.ndarray, offsets=None):
+    a = np.frombuffer(text, dtype=np.uint8) if isinstance(text, (bytes, bytearray)) else text
+    t = torch.from_numpy(np.ascontiguousarray(a).copy()).to(DEV) if len(a) else \
+        torch.empty(0, dtype=torch.uint8, device=DEV)
+    if offsets is None:
+        offsets = [0, len(a)]
+    o = torch.tensor(np.asarray(offsets, dtype=np.int64), device=DEV)
+    return t, o
+
+
+def gpu_count(text, offsets=None, **kw):
+    t, o = to_dev(text, offsets)
+    return wc.count(t, o, **kw)
+
+
+def check(text, offsets=None, per_doc=False, **kw):
+    """Count on the GPU and on the oracle; tables and totals must be identical."""
+    want = oracle.count(text, offsets, per_doc=per_doc)
+    got = gpu_count(text, offsets, per_doc=per_doc, **kw)
+    assert got.total_tokens == want.total
+    g = got.as_dict()
+    w = want.as_dict()
+    if g != w:
+        missing = [k for k in w if k not in g][:5]
+        extra = [k for k in g if k not in w][:5]
+        wrong = [(k, g[k], w[k]) for k in w if k in g and g[k] != w[k]][:5]
+        raise AssertionError(f"mismatch: missing {missing} extra {extra} wrong {wrong}")
+    if per_doc:
+        dp = got.doc_ptr().cpu().numpy()
+        docs = got.docs().cpu().numpy()
+        n_docs = len(offsets) - 1
+        assert len(dp) == n_docs + 1 and dp[0] == 0 and dp[-1] == got.n_entries
+        for d in range(n_docs):
+            assert (docs[dp[d]:dp[d + 1]] == d).all()
+    return got
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def join_docs(docs):
+    text = b"".join(docs)
+    off = np.zeros(len(docs) + 1, dtype=np.int64)
+    np.cumsum([len(d) for d in docs], out=off[1:])
+    return text, off
+
+
+# ------------------------------------------------------------------------------------------
+# the paper's examples
+# ------------------------------------------------------------------------------------------
+
+def test_section2_worked_example():
+    g = golden("section2_worked_example.json")
+    text, off = join_docs([d.encode() for d in g["docs"]])
+    got = check(text, off, count_bytes=4)
+    assert {k.decode(): v for k, v in got.as_dict().items()} == g["reduced"]
+
+
+def test_section2_case_and_punctuation():
+    g = golden("section2_case_punct.json")
+    got = check(g["text"].encode())
+    assert {k.decode(): v for k, v in got.as_dict().items()} == g["expected"]
+
+
+def test_section3_3_grouped_counts():
+    g = golden("section3_3_grouping.json")
+    w = g["word"].encode()
+    text, off = join_docs([b" ".join([w] * n) + b"." for n in g["per_doc"]])
+    per = check(text, off, per_doc=True)
+    assert per.as_dict() == {(d, w): n for d, n in enumerate(g["per_doc"])}
+    assert wc.merge([per]).as_dict() == {w: g["reduced"]}
+
+
+def test_section4_3_applause():
+    g = golden("section4_3_applause.json")
+    check(g["text"].encode())
+
+
+# ------------------------------------------------------------------------------------------
+# brute force and edge cases
+# ------------------------------------------------------------------------------------------
+
+ALPHABET = [b"a", b"Z", b"0", b"'", b" ", b",", b"\x80", b"\n"]
+
+
+def test_every_short_string_as_a_document():
+    docs = [b"".join(p) for n in range(0, 6) for p in itertools.product(ALPHABET, repeat=n)]
+    text, off = join_docs(docs)
+    say("docs", len(docs), "bytes", len(text))
+    check(text, off, per_doc=True)
+    check(text, off)
+
+
+def test_random_text_random_splits():
+    for seed in range(4):
+        text = synth.random_text(300_000, seed, alphabet=b"aAzZ09' ,.\x80\xff\n\t-\"bcY")
+        off = synth.random_splits(len(text), 1 + seed * 97, seed + 100)
+        say("seed", seed)
+        check(text, off)
+
+
+def test_empty_inputs():
+    g = gpu_count(b"")
+    assert g.n_entries == 0 and g.total_tokens == 0
+    g = gpu_count(b"   ,,. \n\x80")
+    assert g.n_entries == 0 and g.total_tokens == 0
+    check(b"a b", [0, 0, 0, 3, 3], per_doc=True)
+    check(b"xxabcabcyy", [2, 5, 8])
+    check(b"xxabcabcyy", [2, 4, 8])
+    t, o = to_dev(b"abc", [0, 0])
+    assert wc.count(t, o).n_entries == 0
+
+
+def test_invalid_offsets_raise():
+    with pytest.raises(wc.WcError) as e:
+        gpu_count(b"abc def", [0, 5, 3])
+    assert e.value.status == wc.WC_EINVAL
+    with pytest.raises(wc.WcError) as e:
+        gpu_count(b"abc", [0, 9])
+    assert e.value.status == wc.WC_EINVAL
+
+
+@pytest.mark.parametrize("stage", [4096, 8192])
+def test_words_across_stage_boundaries(stage):
+    # words of every length 1..40 ending and starting at every position near stage edges
+    rng = np.random.default_rng(stage)
+    parts = []
+    pos = 0
+    while pos < 5 * stage:
+        L = int(rng.integers(1, 41))
+        w = bytes(rng.choice(list(b"abcXYZ019'"), L))
+        sep = bytes(rng.choice(list(b" ,\n."), int(rng.integers(1, 3))))
+        parts.append(w + sep)
+        pos += L + len(sep)
+    text = b"".join(parts)
+    for shift in (0, 1, 7, 15):
+        t = b"q" * shift + text
+        tu = wc.make_tuning(stage_bytes=stage)
+        check(t, tuning=tu)
+        check(t, [0, shift, len(t) // 3, len(t)], tuning=tu)
+
+
+def test_misaligned_corpus_pointer():
+    c = synth.generate("plain-1MB")
+    base = c.text.numpy()[:300_001]
+    want = oracle.count(base).as_dict()
+    for off in range(0, 17):
+        # the view starts `off` bytes into an allocation, so its address is misaligned by
+        # `off`; the byte before it is a word byte ('x') that must not join the first word
+        big = torch.from_numpy(np.concatenate([np.frombuffer(b"x" * off, np.uint8), base]))
+        view = big.to(DEV)[off:]
+        assert view.numel() == len(base)
+        got = wc.count(view, torch.tensor([0, len(base)], device=DEV))
+        assert got.as_dict() == want, off
+        assert got.total_tokens == sum(want.values())
+
+
+def test_long_words():
+    w1 = b"Ab" * 500_000             # 1 MB word, crosses many stages
+    w16 = b"abcdefghijklmnop"
+    w17 = w16 + b"Q"
+    text = b" ".join([w1, w16, w17, w16.upper(), w17, w1.lower(), b"x", w1]) + b" "
+    check(text)
+    check(text, [0, 1_000_001, len(text)])
+    check(text, per_doc=True, offsets=[0, 1_000_001, len(text)])
+
+
+def test_single_word_vocabulary_max_contention():
+    text = b"the " * 400_000
+    got = check(text)
+    assert got.as_dict() == {b"the": 400_000}
+
+
+@pytest.mark.parametrize("bits", [1, 4, 8])
+def test_forced_key_collisions(bits):
+    c = synth.generate("plain-1MB")
+    text = c.text.numpy()[:200_000]
+    check(text, debug_hash_bits=bits)
+    check(np.frombuffer(b"ab abc abcd abcdefghijklmnopqrs abcdefghijklmnopqrt " * 50, np.uint8),
+          debug_hash_bits=bits)
+
+
+def test_table_regrow():
+    c = synth.generate("plain-1MB")
+    text = c.text.numpy()
+    got = check(text, table_slots=64)      # far too small: grows until it fits
+    assert got.res.table_slots > 4096
+    with pytest.raises(wc.WcError) as e:
+        gpu_count(text, table_slots=64, regrow=False)
+    assert e.value.status == wc.WC_ETABLEFULL
+
+
+def test_word_capacity_regrow():
+    text = b" ".join(b"w%07d" % i for i in range(20_000))
+    check(text, word_bytes_cap=16)
+
+
+@pytest.mark.parametrize("stage,lds,policy,grid,no_lds", [
+    (8192, 2048, wc.WC_FLUSH_ALL, 0, False),
+    (4096, 256, wc.WC_FLUSH_ALL, 0, False),
+    (8192, 4096, wc.WC_FLUSH_BYPASS, 0, False),
+    (4096, 1024, wc.WC_FLUSH_BYPASS, 3, False),
+    (8192, 2048, wc.WC_FLUSH_ALL, 1, False),
+    (8192, 2048, wc.WC_FLUSH_ALL, 0, True),
+])
+def test_tuning_points_agree(stage, lds, policy, grid, no_lds):
+    c = synth.generate("plain-1MB")
+    tu = wc.make_tuning(stage_bytes=stage, lds_entries=lds, flush_policy=policy,
+                        grid_blocks=grid)
+    flags = wc.WC_DEBUG_NO_LDS if no_lds else 0
+    check(c.text.numpy(), c.offsets.numpy(), tuning=tu, debug_flags=flags)
+
+
+# ------------------------------------------------------------------------------------------
+# synthetic workloads
+# ------------------------------------------------------------------------------------------
+
+def test_plain_1mb_int32():
+    c = synth.generate("plain-1MB")
+    got = check(c.text.numpy(), c.offsets.numpy(), count_bytes=4)
+    assert got.as_dict() == c.expected_table()
+    assert got.counts().dtype == torch.int32
+
+
+def test_corpora():
+    for c in synth.generate("corpora-4x2000", scale=0.25):
+        check(c.text.numpy(), c.offsets.numpy(), count_bytes=4)
+
+
+def test_per_doc_batched_sample():
+    c = synth.generate("batched-100k", scale=0.003)
+    say("docs", len(c.offsets) - 1, "bytes", len(c.text))
+    check(c.text.numpy(), c.offsets.numpy(), per_doc=True, count_bytes=4)
+
+
+def test_stream_piece():
+    c = synth.generate("stream-8GiB", scale=1 / 256)
+    got = check(c.text.numpy(), c.offsets.numpy())
+    assert got.as_dict() == c.expected_table()
+
+
+def test_stream_full_size_against_rank_histogram():
+    """8 GiB single document, S = 2^22, int64: every count equals the generator's histogram."""
+    say("generating 8 GiB on the GPU")
+    c = synth.generate("stream-8GiB", device=DEV)
+    say("generated", c.n_tokens, "tokens")
+    got = wc.count(c.text, c.offsets, count_bytes=8, table_slots=1 << 22)
+    assert got.total_tokens == c.n_tokens
+    w, o, cnt, _ = got.to_host()
+    # map each exported word to its vocabulary rank through a dictionary of the vocabulary
+    vocab = {bytes(c.vocab[k, :c.vocab_lens[k]]): k for k in range(len(c.vocab_lens))}
+    wb = w.tobytes()
+    ranks = np.array([vocab[wb[o[e]:o[e + 1]]] for e in range(len(cnt))], dtype=np.int64)
+    exp = c.expected.cpu().numpy()
+    assert len(ranks) == int((exp > 0).sum())
+    assert np.array_equal(cnt, exp[ranks])
+    del c
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------------------------------
+# merge, top-k, hash
+# ------------------------------------------------------------------------------------------
+
+def test_merge_matches_oracle():
+    c = synth.generate("plain-1MB")
+    text, off = c.text.numpy(), c.offsets.numpy()
+    per = gpu_count(text, off, per_doc=True, count_bytes=4)
+    whole = oracle.count(text, off).as_dict()
+    assert wc.merge([per]).as_dict() == whole
+    singles = [gpu_count(text[off[i]:off[i + 1]]) for i in range(len(off) - 1)]
+    assert wc.merge(singles).as_dict() == whole
+    a = wc.merge([wc.merge(singles[:2]), wc.merge(singles[2:])])
+    assert a.as_dict() == whole
+    g = golden("section2_worked_example.json")
+    parts = []
+    for p in g["partials"]:
+        t = b" ".join(w.encode() for w, n in p.items() for _ in range(n))
+        parts.append(gpu_count(t))
+    assert {k.decode(): v for k, v in wc.merge(parts).as_dict().items()} == g["reduced"]
+
+
+def test_merge_long_words_and_collisions():
+    w = b"Q" * 40
+    t1 = gpu_count(b" ".join([w, w.lower(), b"a" * 17, b"b"]))
+    t2 = gpu_count(b" ".join([w, b"a" * 17, b"c"]))
+    assert wc.merge([t1, t2]).as_dict() == {w.lower(): 3, b"a" * 17: 2, b"b": 1, b"c": 1}
+
+
+def test_topk_matches_oracle():
+    cs = synth.generate("corpora-4x2000", scale=0.1)
+    tabs = [gpu_count(c.text.numpy(), c.offsets.numpy(), count_bytes=4) for c in cs]
+    otabs = [oracle.count(c.text.numpy(), c.offsets.numpy()) for c in cs]
+    for k, mc in ((50, 1), (7, 3), (300, 1)):
+        got = wc.topk_ratio(tabs, k, mc)
+        want = oracle.topk_ratio(otabs, k, mc)
+        assert got.vocab_size == want.vocab_size
+        for c in range(len(cs)):
+            assert got.words[c] == want.words[c]
+            assert list(got.n_c[c]) == list(map(int, want.n_c[c]))
+            assert list(got.n_rest[c]) == list(map(int, want.n_rest[c]))
+            np.testing.assert_allclose(got.score[c], want.score[c], rtol=1e-12)
+
+
+def test_topk_ties_and_small_tables():
+    tabs = [gpu_count(b"a b c a"), gpu_count(b"b c d"), gpu_count(b"a d d e")]
+    otabs = [oracle.count(b"a b c a"), oracle.count(b"b c d"), oracle.count(b"a d d e")]
+    for k in (1, 2, 5, 10):
+        got = wc.topk_ratio(tabs, k)
+        want = oracle.topk_ratio(otabs, k)
+        assert got.words == want.words
+
+
+def test_fnv1a_published_vectors():
+    # FNV-1a 64 test vectors from the FNV reference (Fowler, Noll, Vo)
+    h = wc.hash_words([b"", b"a", b"foobar"])
+    assert h == [0xcbf29ce484222325, 0xaf63dc4c8601ec8c, 0x85944171f73967e8]
+    # folding: the hash is taken over folded bytes
+    assert wc.hash_words([b"FooBar"]) == [0x85944171f73967e8]
