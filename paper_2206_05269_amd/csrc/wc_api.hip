@@ -16,6 +16,9 @@ thread_local int32_t g_last_hip = 0;
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultLds = 2048;
 constexpr uint32_t kDefaultBlock = 512;
+constexpr uint32_t kSpillLds = 4096;          // pass-1 LDS table entries
+constexpr uint32_t kReduceLds = 7680;         // pass-2 LDS table entries (150 KiB)
+constexpr uint64_t kSpillMinBytes = 64ull << 20;
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
@@ -106,8 +109,21 @@ struct CountLayout {
   // per-document
   uint64_t *docs, *doc_ptr, *list_docs, *list_slots, *sorted_docs, *sorted_slots, *lens;
   void* cub;
+  // two-pass global count
+  bool spill = false;
+  uint32_t spill_grid = 0, R = 0;
+  uint4* arena = nullptr;
+  uint32_t* cursor = nullptr;
+  uint16_t* fill = nullptr;
   uint64_t total;
 };
+
+bool use_spill(uint64_t len, const wc_opts* o) {
+  if (o->mode != WC_GLOBAL) return false;
+  if (o->debug_flags & WC_DEBUG_SPILL) return true;
+  if (o->debug_flags & (WC_DEBUG_DIRECT | WC_DEBUG_NO_LDS)) return false;
+  return len >= kSpillMinBytes;
+}
 
 int64_t base_offset(const uint8_t* corpus) {
   return -(int64_t)((uintptr_t)corpus & 15);
@@ -157,6 +173,20 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
     L->scan_bytes = b;
     L->cub = B.take<uint8_t>(std::max(a, b));
   }
+  L->spill = use_spill(len, o) && L->n_stages > 0;
+  if (L->spill) {
+    uint32_t grid = tu.grid ? tu.grid : (uint32_t)device_cus();
+    if (grid > L->n_stages) grid = (uint32_t)L->n_stages;
+    L->spill_grid = grid;
+    // room for every byte of text as spilled records, plus one open block per workgroup and
+    // partition; a partition that still runs out counts in the global table instead
+    uint64_t blk_bytes = (uint64_t)kBlockRec * 16;
+    uint64_t need = len + (uint64_t)grid * kSpillParts * blk_bytes;
+    L->R = (uint32_t)((need + (uint64_t)kSpillParts * blk_bytes - 1) / ((uint64_t)kSpillParts * blk_bytes));
+    L->arena = B.take<uint4>((uint64_t)kSpillParts * L->R * blk_bytes);
+    L->cursor = B.take<uint32_t>(kSpillParts * 4);
+    L->fill = B.take<uint16_t>((uint64_t)kSpillParts * L->R * 2);
+  }
   L->total = B.off;
   return true;
 }
@@ -181,10 +211,15 @@ struct Timer {
   }
 };
 
+size_t spill_count_dyn(uint32_t E) {
+  return (size_t)E * 20 + (size_t)kSpillParts * kStageRec * 16 + 3 * (size_t)kSpillParts * 4;
+}
+
 hipError_t ensure_smem_attr() {
   static hipError_t once = [] {
     hipError_t e = set_count_smem(512, 160 * 1024 - 40 * 1024);
     if (e == hipSuccess) e = set_count_smem(256, 160 * 1024 - 24 * 1024);
+    if (e == hipSuccess) e = set_spill_smem(spill_count_dyn(kSpillLds), (size_t)kReduceLds * 20);
     return e;
   }();
   return once;
@@ -283,9 +318,42 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
     P.policy = tu.policy;
     P.no_lds = (opts->debug_flags & WC_DEBUG_NO_LDS) ? 1u : 0u;
     size_t dyn = (size_t)tu.lds * (per_doc ? 24 : 20);
-    if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
-    HIPCHK(launch_count(P, per_doc, grid, tu.block, dyn, s));
-    if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
+    if (!L.spill) {
+      if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
+      HIPCHK(launch_count(P, per_doc, grid, tu.block, dyn, s));
+      if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
+    } else {
+      SpillParams Q;
+      Q.corpus = d_corpus;
+      Q.len = corpus_len;
+      Q.offsets = d_offsets;
+      Q.n_docs = n_docs;
+      Q.table = L.table;
+      Q.mask = L.S - 1;
+      Q.occ_limit = occ_limit;
+      Q.key_mask = key_mask_of(opts);
+      Q.hdr = L.hdr;
+      Q.stage_doc = L.stage_doc;
+      Q.base_off = b0;
+      Q.n_stages = L.n_stages;
+      uint32_t sg = L.spill_grid;
+      Q.stages_per_wg = (L.n_stages + sg - 1) / sg;
+      sg = (uint32_t)((L.n_stages + Q.stages_per_wg - 1) / Q.stages_per_wg);
+      uint32_t E = opts->tuning && opts->tuning->lds_entries ? tu.lds : kSpillLds;
+      uint32_t pct = opts->tuning && opts->tuning->lds_load_pct ? opts->tuning->lds_load_pct : 75;
+      Q.lds_entries = E;
+      Q.hot_cap = std::max<uint32_t>(1, (uint32_t)((uint64_t)E * pct / 100));
+      Q.reduce_entries = kReduceLds;
+      Q.R = L.R;
+      Q.arena = L.arena;
+      Q.cursor = L.cursor;
+      Q.fill = L.fill;
+      HIPCHK(launch_fill_zero(L.cursor, kSpillParts * 4, s));
+      if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
+      HIPCHK(launch_spill_count(Q, sg, spill_count_dyn(E), s));
+      if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
+      HIPCHK(launch_spill_reduce(Q, (size_t)kReduceLds * 20, s));
+    }
   }
 
   ExportParams E;

@@ -111,43 +111,6 @@ WC_DEV uint64_t short_key(uint64_t lo, uint64_t hi, uint32_t doc1, uint64_t key_
   return finish_key(h, key_mask);
 }
 
-// Scan a word from logical position s (its first byte) in device memory, up to `limit`
-// (exclusive; the document end) or the first non-word byte. Returns the length, the packed
-// bytes when the length is <= 16, and the FNV-1a 64 hash of the folded bytes.
-WC_DEV uint64_t scan_word(const uint8_t* corpus, uint64_t s, uint64_t limit, uint64_t* plo,
-                          uint64_t* phi, uint64_t* pfnv) {
-  uint64_t h = kFnvOffset, lo = 0, hi = 0, n = 0;
-  uint64_t p = s;
-  bool done = false;
-  while (!done && p < limit) {
-    // the aligned 16-byte block containing p, when it lies inside [corpus, corpus + limit);
-    // otherwise single bytes (limit <= corpus length, so no byte past the buffer is read)
-    uintptr_t a = ((uintptr_t)(corpus + p)) & ~(uintptr_t)15;
-    uint32_t first = (uint32_t)((uintptr_t)(corpus + p) - a);
-    uint32_t wds[4];
-    bool vec = a >= (uintptr_t)corpus && a + 16 <= (uintptr_t)(corpus + limit);
-    if (vec) {
-      uint4 v = *(const uint4*)a;
-      wds[0] = v.x; wds[1] = v.y; wds[2] = v.z; wds[3] = v.w;
-    }
-    for (uint32_t j = first; j < 16; ++j) {
-      if (p >= limit) { done = true; break; }
-      uint32_t b = vec ? (wds[j >> 2] >> ((j & 3) * 8)) & 0xffu : (uint32_t)corpus[p];
-      if (!is_word_byte(b)) { done = true; break; }
-      uint32_t f = fold_byte(b);
-      h = fnv_step(h, f);
-      if (n < 8) lo |= (uint64_t)f << (8 * n);
-      else if (n < 16) hi |= (uint64_t)f << (8 * (n - 8));
-      ++n;
-      ++p;
-    }
-  }
-  *plo = lo;
-  *phi = hi;
-  *pfnv = h;
-  return n;
-}
-
 template <int BLOCK, bool kPerDoc>
 __global__ __launch_bounds__(BLOCK) void count_kernel(CountParams P) {
   constexpr int STAGE = BLOCK * 16;

@@ -30,6 +30,38 @@ struct CountParams {
   uint32_t no_lds;
 };
 
+// two-pass global count (wc_spill.hip)
+constexpr uint32_t kSpillParts = 256;  // partitions of the spilled records
+constexpr uint32_t kStageRec = 8;      // records staged per partition in LDS (128 bytes)
+constexpr uint32_t kBlockRec = 256;    // records per arena block (4 KiB)
+constexpr uint32_t kSpillList = 512;   // records a stage can spill before the fallback
+
+struct SpillParams {
+  const uint8_t* corpus;
+  uint64_t len;
+  const uint64_t* offsets;
+  uint64_t n_docs;
+  Slot* table;
+  uint64_t mask;
+  uint64_t occ_limit;
+  uint64_t key_mask;
+  Header* hdr;
+  const uint64_t* stage_doc;
+  int64_t base_off;
+  uint64_t n_stages;
+  uint64_t stages_per_wg;
+  uint32_t lds_entries;      // pass-1 LDS table entries (<= 4096)
+  uint32_t hot_cap;          // pass-1 live entries before eviction
+  uint32_t reduce_entries;   // pass-2 LDS table entries
+  uint32_t R;                // arena blocks per partition
+  uint4* arena;              // [kSpillParts][R][kBlockRec] records
+  uint32_t* cursor;          // [kSpillParts] blocks taken per partition
+  uint16_t* fill;            // [kSpillParts][R] records per block
+};
+hipError_t set_spill_smem(size_t count_dyn, size_t reduce_dyn);
+hipError_t launch_spill_count(const SpillParams& P, uint32_t grid, size_t dyn, hipStream_t s);
+hipError_t launch_spill_reduce(const SpillParams& P, size_t dyn, hipStream_t s);
+
 hipError_t launch_count(const CountParams& P, bool per_doc, uint32_t grid, uint32_t block,
                         size_t dyn, hipStream_t s);
 hipError_t set_count_smem(uint32_t block, size_t dyn);

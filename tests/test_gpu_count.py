@@ -68,6 +68,9 @@ def check(text, offsets=None, per_doc=False, **kw):
     return got
 
 
+PATHS = {"direct": wc.WC_DEBUG_DIRECT, "spill": wc.WC_DEBUG_SPILL}
+
+
 def golden(name):
     with open(os.path.join(GOLDEN, name)) as f:
         return json.load(f)
@@ -126,12 +129,13 @@ def test_every_short_string_as_a_document():
     check(text, off)
 
 
-def test_random_text_random_splits():
+@pytest.mark.parametrize("path", ["direct", "spill"])
+def test_random_text_random_splits(path):
     for seed in range(4):
         text = synth.random_text(300_000, seed, alphabet=b"aAzZ09' ,.\x80\xff\n\t-\"bcY")
         off = synth.random_splits(len(text), 1 + seed * 97, seed + 100)
-        say("seed", seed)
-        check(text, off)
+        say("seed", seed, path)
+        check(text, off, debug_flags=PATHS[path])
 
 
 def test_empty_inputs():
@@ -155,8 +159,9 @@ def test_invalid_offsets_raise():
     assert e.value.status == wc.WC_EINVAL
 
 
+@pytest.mark.parametrize("path", ["direct", "spill"])
 @pytest.mark.parametrize("stage", [4096, 8192])
-def test_words_across_stage_boundaries(stage):
+def test_words_across_stage_boundaries(stage, path):
     # words of every length 1..40 ending and starting at every position near stage edges
     rng = np.random.default_rng(stage)
     parts = []
@@ -168,11 +173,13 @@ def test_words_across_stage_boundaries(stage):
         parts.append(w + sep)
         pos += L + len(sep)
     text = b"".join(parts)
+    if path == "spill" and stage != 8192:
+        pytest.skip("the two-pass kernel scans 8 KiB stages")
     for shift in (0, 1, 7, 15):
         t = b"q" * shift + text
         tu = wc.make_tuning(stage_bytes=stage)
-        check(t, tuning=tu)
-        check(t, [0, shift, len(t) // 3, len(t)], tuning=tu)
+        check(t, tuning=tu, debug_flags=PATHS[path])
+        check(t, [0, shift, len(t) // 3, len(t)], tuning=tu, debug_flags=PATHS[path])
 
 
 def test_misaligned_corpus_pointer():
@@ -190,29 +197,32 @@ def test_misaligned_corpus_pointer():
         assert got.total_tokens == sum(want.values())
 
 
-def test_long_words():
+@pytest.mark.parametrize("path", ["direct", "spill"])
+def test_long_words(path):
     w1 = b"Ab" * 500_000             # 1 MB word, crosses many stages
     w16 = b"abcdefghijklmnop"
     w17 = w16 + b"Q"
     text = b" ".join([w1, w16, w17, w16.upper(), w17, w1.lower(), b"x", w1]) + b" "
-    check(text)
-    check(text, [0, 1_000_001, len(text)])
+    check(text, debug_flags=PATHS[path])
+    check(text, [0, 1_000_001, len(text)], debug_flags=PATHS[path])
     check(text, per_doc=True, offsets=[0, 1_000_001, len(text)])
 
 
-def test_single_word_vocabulary_max_contention():
+@pytest.mark.parametrize("path", ["direct", "spill"])
+def test_single_word_vocabulary_max_contention(path):
     text = b"the " * 400_000
-    got = check(text)
+    got = check(text, debug_flags=PATHS[path])
     assert got.as_dict() == {b"the": 400_000}
 
 
+@pytest.mark.parametrize("path", ["direct", "spill"])
 @pytest.mark.parametrize("bits", [1, 4, 8])
-def test_forced_key_collisions(bits):
+def test_forced_key_collisions(bits, path):
     c = synth.generate("plain-1MB")
     text = c.text.numpy()[:200_000]
-    check(text, debug_hash_bits=bits)
+    check(text, debug_hash_bits=bits, debug_flags=PATHS[path])
     check(np.frombuffer(b"ab abc abcd abcdefghijklmnopqrs abcdefghijklmnopqrt " * 50, np.uint8),
-          debug_hash_bits=bits)
+          debug_hash_bits=bits, debug_flags=PATHS[path])
 
 
 def test_table_regrow():
@@ -246,20 +256,44 @@ def test_tuning_points_agree(stage, lds, policy, grid, no_lds):
     check(c.text.numpy(), c.offsets.numpy(), tuning=tu, debug_flags=flags)
 
 
+@pytest.mark.parametrize("lds,grid,pct", [(256, 0, 75), (256, 1, 50), (1024, 3, 90),
+                                          (4096, 0, 75), (512, 7, 10)])
+def test_spill_tuning_points(lds, grid, pct):
+    """Small LDS tables force evictions at every stage; tiny grids force long ranges."""
+    c = synth.generate("plain-1MB")
+    tu = wc.make_tuning(lds_entries=lds, grid_blocks=grid, lds_load_pct=pct)
+    check(c.text.numpy(), c.offsets.numpy(), tuning=tu, debug_flags=wc.WC_DEBUG_SPILL)
+    cs = synth.generate("corpora-4x2000", scale=0.05)
+    check(cs[0].text.numpy(), cs[0].offsets.numpy(), tuning=tu, debug_flags=wc.WC_DEBUG_SPILL)
+
+
+def test_spill_heavy_counts():
+    """Records with counts above one (evictions, final flushes) and counts above 32767."""
+    rng = np.random.default_rng(5)
+    words = [b"w%d" % i for i in range(3000)]
+    idx = np.minimum(rng.zipf(1.3, size=300_000), 3000) - 1
+    text = b" ".join(words[i] for i in idx) + b" " + b"the " * 100_000
+    tu = wc.make_tuning(lds_entries=512, lds_load_pct=60)
+    check(text, tuning=tu, debug_flags=wc.WC_DEBUG_SPILL)
+    check(text, tuning=wc.make_tuning(grid_blocks=1), debug_flags=wc.WC_DEBUG_SPILL)
+
+
 # ------------------------------------------------------------------------------------------
 # synthetic workloads
 # ------------------------------------------------------------------------------------------
 
-def test_plain_1mb_int32():
+@pytest.mark.parametrize("path", ["direct", "spill"])
+def test_plain_1mb_int32(path):
     c = synth.generate("plain-1MB")
-    got = check(c.text.numpy(), c.offsets.numpy(), count_bytes=4)
+    got = check(c.text.numpy(), c.offsets.numpy(), count_bytes=4, debug_flags=PATHS[path])
     assert got.as_dict() == c.expected_table()
     assert got.counts().dtype == torch.int32
 
 
-def test_corpora():
+@pytest.mark.parametrize("path", ["direct", "spill"])
+def test_corpora(path):
     for c in synth.generate("corpora-4x2000", scale=0.25):
-        check(c.text.numpy(), c.offsets.numpy(), count_bytes=4)
+        check(c.text.numpy(), c.offsets.numpy(), count_bytes=4, debug_flags=PATHS[path])
 
 
 def test_per_doc_batched_sample():
@@ -268,9 +302,10 @@ def test_per_doc_batched_sample():
     check(c.text.numpy(), c.offsets.numpy(), per_doc=True, count_bytes=4)
 
 
-def test_stream_piece():
+@pytest.mark.parametrize("path", ["direct", "spill"])
+def test_stream_piece(path):
     c = synth.generate("stream-8GiB", scale=1 / 256)
-    got = check(c.text.numpy(), c.offsets.numpy())
+    got = check(c.text.numpy(), c.offsets.numpy(), debug_flags=PATHS[path])
     assert got.as_dict() == c.expected_table()
 
 
