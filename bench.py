@@ -51,6 +51,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 8 GiB corpus")
     ap.add_argument("--cpu-sample-mb", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--plain-docs", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -131,7 +133,62 @@ def main():
         sample = min(B, args.cpu_sample_mb << 20)
         log(f"timing the oracle on {sample} bytes")
         out["cpu_baseline"] = cpu_baseline(c.text, sample)
+    del c, ws, r
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_docs_per_s(args.steps, args.warmup, args.plain_docs)
     print(json.dumps(out), flush=True)
+
+
+def batched_docs_per_s(steps: int, warmup: int, plain_docs: int):
+    """Workload "batched-100k": 100,000 documents (lognormal sizes, median 16 KiB, clipped to
+    200 B..1 MiB; 200,000-word vocabulary, Zipf 1.1), one table per document. Batched = one
+    captured graph replay per corpus; plain = one wc_count call per document."""
+    import torch
+    from paper_2206_05269_amd import synth, wc
+    name = "batched-100k"
+    log(f"generating {name} on the GPU")
+    c = synth.generate(name, device="cuda:0")
+    torch.cuda.synchronize()
+    n_docs = c.offsets.numel() - 1
+    B = c.text.numel()
+    b = wc.Batch(max_docs=n_docs, max_bytes=B, count_bytes=4)
+    for _ in range(warmup):
+        r = b.run(c.text, c.offsets)
+    if r.total_tokens != c.n_tokens:
+        log(f"MISMATCH batched tokens {r.total_tokens} vs {c.n_tokens}")
+        sys.exit(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = b.run(c.text, c.offsets)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / steps
+    entries = r.n_entries
+    b.close()
+    # plain: one launch (wc_count, global table of that document) per document
+    off = c.offsets.cpu().numpy()
+    m = min(plain_docs, n_docs)
+    plan = wc.count_plan(int(off[m] - off[0]), 1, count_bytes=4)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda:0")
+    doc_off = [torch.tensor([0, int(off[d + 1] - off[d])], dtype=torch.int64, device="cuda:0")
+               for d in range(m)]
+    for d in range(min(20, m)):
+        wc.count(c.text[off[d]:off[d + 1]], doc_off[d], count_bytes=4, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in range(m):
+        wc.count(c.text[off[d]:off[d + 1]], doc_off[d], count_bytes=4, workspace=ws)
+    torch.cuda.synchronize()
+    dt_p = (time.perf_counter() - t0) / m
+    res = {"workload": name, "docs": n_docs, "bytes": B, "tokens": c.n_tokens,
+           "doc_word_pairs": entries,
+           "batched_docs_per_s": round(n_docs / dt_b, 1), "batched_ms": round(dt_b * 1e3, 3),
+           "batched_GBps": round(B / dt_b / 1e9, 2),
+           "plain_docs_per_s": round(1.0 / dt_p, 1), "plain_sample_docs": m,
+           "speedup": round((n_docs / dt_b) * dt_p, 1)}
+    log(f"batched {res['batched_docs_per_s']} docs/s vs plain {res['plain_docs_per_s']} docs/s")
+    return res
 
 
 if __name__ == "__main__":

@@ -71,8 +71,9 @@ typedef struct wc_tuning {
   uint32_t lds_entries;   /* LDS table entries per workgroup, power of two, 256..4096 */
   uint32_t flush_policy;  /* WC_FLUSH_ALL or WC_FLUSH_BYPASS */
   uint32_t grid_blocks;   /* workgroups in the count launch (0 = 2 per CU) */
-  uint32_t lds_load_pct;  /* WC_FLUSH_ALL: flush when the LDS table is this % full (0 = 50) */
-  uint32_t reserved;
+  uint32_t lds_load_pct;  /* LDS table load at which it is flushed / relieved (0 = default) */
+  uint32_t chunk_bytes;   /* per-document mode: bytes per work item, power of two in
+                             16 KiB..1 MiB (0 = 64 KiB) */
 } wc_tuning;
 
 typedef struct wc_opts {
@@ -95,8 +96,9 @@ typedef struct wc_plan {
 
 /* A word table in device memory: entry e is the folded word
  * d_words[d_word_offsets[e] .. d_word_offsets[e+1]) with count d_counts[e]. Entry order is
- * unspecified. Per-document tables are grouped by document: entries of document d are
- * [d_doc_ptr[d], d_doc_ptr[d+1]) and d_docs[e] is the entry's document. */
+ * unspecified. Per-document tables are grouped by document: the entries of document d are
+ * the d_doc_len[d] entries starting at d_doc_ptr[d]; documents follow each other in an
+ * unspecified order; d_docs[e] is the document of entry e. */
 typedef struct wc_result {
   uint64_t n_entries;
   uint64_t total_tokens;     /* tokens counted (= sum of counts) */
@@ -108,7 +110,8 @@ typedef struct wc_result {
   uint64_t* d_word_offsets;  /* uint64[n_entries + 1] */
   uint8_t* d_words;          /* uint8[word_bytes] */
   void* d_counts;            /* int32 or int64 [n_entries] */
-  uint64_t* d_doc_ptr;       /* WC_PER_DOC: uint64[n_docs + 1], else NULL */
+  uint64_t* d_doc_ptr;       /* WC_PER_DOC: uint64[n_docs] first entry of each document */
+  uint64_t* d_doc_len;       /* WC_PER_DOC: uint64[n_docs] entries of each document */
   uint64_t* d_docs;          /* WC_PER_DOC: uint64[n_entries], else NULL */
   float kernel_ms;           /* WC_DEBUG_TIME: duration of the count (or merge) kernel */
   float total_ms;            /* WC_DEBUG_TIME: duration of the whole call on the device */
@@ -185,6 +188,95 @@ wc_status wc_topk_ratio_plan(const wc_result* const* corpora, uint32_t n_corpora
 wc_status wc_topk_ratio(const wc_result* const* corpora, uint32_t n_corpora, uint32_t k,
                         uint64_t min_count, void* d_workspace, uint64_t workspace_bytes,
                         wc_topk* out, void* stream);
+
+/* Batched per-document counting (Section 3.1 counts every document in its own dictionary):
+ * all documents of a corpus are counted into per-document tables by one persistent launch
+ * that takes 64 KiB windows of documents from a device-side queue. The first wc_batch_run
+ * captures the whole call (task upload, clears, kernels, size readback) into a HIP graph; later
+ * runs only update a pinned host task description and replay the graph, so a run makes no
+ * allocation and one graph launch. Device memory is the caller's workspace of
+ * wc_batch_plan() bytes, sized for at most max_docs documents of max_bytes bytes in total
+ * (max_bytes < 2^32). The batch object itself holds only host-side resources (a stream, pinned
+ * host memory, the graph). Results point into the workspace and stay valid until the next run.
+ * opts->mode must be WC_PER_DOC; opts->tuning selects lds_entries and grid_blocks. */
+typedef struct wc_batch wc_batch;
+
+wc_status wc_batch_plan(const wc_opts* opts, uint64_t max_docs, uint64_t max_bytes,
+                        uint64_t* workspace_bytes);
+
+wc_status wc_batch_create(const wc_opts* opts, uint64_t max_docs, uint64_t max_bytes,
+                          void* d_workspace, uint64_t workspace_bytes, wc_batch** out);
+
+/* Count one corpus (device pointers, as wc_count). The caller's stream is ordered before the
+ * graph launch and the call returns after the results are complete. Errors: WC_EINVAL
+ * (larger than the plan, invalid offsets), WC_ENOMEM (outputs or private tables short: plan
+ * with larger word_bytes_cap / table_slots), WC_ETABLEFULL, WC_EOVERFLOW, WC_EDEVICE. */
+wc_status wc_batch_run(wc_batch* b, const uint8_t* d_corpus, uint64_t corpus_len,
+                       const uint64_t* d_offsets, uint64_t n_docs, wc_result* out, void* stream);
+
+wc_status wc_batch_destroy(wc_batch* b);
+
+/* Serving. A server counts texts submitted at any time and keeps each result resident on
+ * the device until released, answering merge queries over resident tables. It owns one
+ * device pool of mem_budget bytes (allocated at creation); a request waits for admission
+ * until the memory its count needs is free (requests larger than the budget fail with
+ * WC_ENOMEM at submission; when the pool is held by resident tables and nothing is running,
+ * the request fails with WC_ENOMEM instead of waiting). max_streams worker threads (1..16)
+ * each drive one HIP stream, so admitted requests overlap on the device; small
+ * single-document requests queued together are counted in one per-document launch and split
+ * into one table per request. Results are global word tables in the server's memory, valid
+ * until wc_server_release(id). Thread-safe: submit/poll/wait/merge/release may be called from
+ * any host thread. */
+typedef struct wc_server wc_server;
+
+wc_status wc_server_create(int device, uint64_t mem_budget, uint32_t max_streams,
+                           wc_server** out);
+
+/* Submit a count: text (host memory, copied at submission, or device memory that must stay
+ * valid until the request completes when text_on_device != 0), host offsets[n_docs + 1].
+ * opts->mode must be WC_GLOBAL. Returns the request id in *req_id. */
+wc_status wc_server_submit(wc_server* s, const uint8_t* text, uint64_t len,
+                           const uint64_t* offsets, uint64_t n_docs, int text_on_device,
+                           const wc_opts* opts, uint64_t* req_id);
+
+/* WC_EAGAIN until request id is complete; then its status, and *out describes its table. */
+wc_status wc_server_poll(wc_server* s, uint64_t id, wc_result* out);
+
+/* Block until request id is complete; its status, and *out describes its table. */
+wc_status wc_server_wait(wc_server* s, uint64_t id, wc_result* out);
+
+/* Host clock times (seconds, steady clock) of submission, start and completion. */
+wc_status wc_server_times(wc_server* s, uint64_t id, double* submit_s, double* start_s,
+                          double* done_s);
+
+/* Queue the merge of k completed resident tables (Section 3.3) into a new resident table. */
+wc_status wc_server_merge(wc_server* s, const uint64_t* ids, uint32_t k, const wc_opts* opts,
+                          uint64_t* new_id);
+
+/* Wait for request id, then free its resident table. */
+wc_status wc_server_release(wc_server* s, uint64_t id);
+
+/* Count launches the server has made (packing makes this smaller than the requests). */
+uint64_t wc_server_launches(wc_server* s);
+
+wc_status wc_server_destroy(wc_server* s);
+
+/* Autotuner: time wc_count on a calibration sample (device-resident, as wc_count) for each
+ * point of a small grid of launch tunings (per-document mode: work-item bytes x LDS entries x
+ * relief load; global mode: LDS entries x load) with HIP events on `stream`, and return the
+ * fastest in *best (its time per call in *best_ms). The workspace must hold
+ * wc_autotune_plan() bytes. The sample's counts are not returned. */
+wc_status wc_autotune_plan(uint64_t len, uint64_t n_docs, const wc_opts* opts,
+                           uint64_t* workspace_bytes);
+wc_status wc_autotune(const uint8_t* d_sample, uint64_t len, const uint64_t* d_offsets,
+                      uint64_t n_docs, const wc_opts* opts, void* d_workspace,
+                      uint64_t workspace_bytes, wc_tuning* best, float* best_ms, void* stream);
+
+/* Copy a table to host buffers (synchronous): word_offsets[n_entries + 1] (as stored),
+ * words[word_bytes] (starting at d_words[d_word_offsets[0]]), counts[n_entries] (count_bytes
+ * each). Any output pointer may be NULL to skip it. */
+wc_status wc_table_to_host(const wc_result* t, uint64_t* word_offsets, uint8_t* words,
+                           void* counts);
 
 /* FNV-1a 64 (Fowler, Noll, Vo) of n byte strings on the device: d_out[i] = FNV-1a 64 of
  * fold(d_bytes[d_offsets[i] .. d_offsets[i+1])), computed by the same device function the

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "wc_internal.h"
 
@@ -51,7 +52,7 @@ struct Bump {
 };
 
 struct Tune {
-  uint32_t block, stage, lds, policy, grid, flush_at;
+  uint32_t block, stage, lds, policy, grid, flush_at, pct, chunk;
 };
 
 int device_cus() {
@@ -78,7 +79,10 @@ bool resolve_tuning(const wc_tuning* t, Tune* out) {
   u.grid = t ? t->grid_blocks : 0;
   uint32_t pct = t && t->lds_load_pct ? t->lds_load_pct : 50;
   if (pct > 100) return false;
+  u.pct = t && t->lds_load_pct ? t->lds_load_pct : 0;
   u.flush_at = (uint32_t)((uint64_t)u.lds * pct / 100);
+  u.chunk = t && t->chunk_bytes ? t->chunk_bytes : (uint32_t)kWin;
+  if (!is_pow2(u.chunk) || u.chunk < kMinWin || u.chunk > (1u << 20)) return false;
   *out = u;
   return true;
 }
@@ -107,7 +111,7 @@ struct CountLayout {
   void* counts;
   uint8_t* words;
   // per-document
-  uint64_t *docs, *doc_ptr, *list_docs, *list_slots, *sorted_docs, *sorted_slots, *lens;
+  uint64_t *docs, *doc_ptr, *doc_len, *list_docs, *list_slots, *sorted_docs, *sorted_slots, *lens;
   void* cub;
   // two-pass global count
   bool spill = false;
@@ -127,6 +131,74 @@ bool use_spill(uint64_t len, const wc_opts* o) {
 
 int64_t base_offset(const uint8_t* corpus) {
   return -(int64_t)((uintptr_t)corpus & 15);
+}
+
+// Per-document count (document-centric kernel): outputs and private tables of large documents.
+struct DocLayout {
+  uint64_t n_win, cap_e, cap_b, arena_slots;
+  Header* hdr;
+  DocTask* task;
+  uint64_t* win_doc;
+  uint64_t* woff;
+  uint8_t* words;
+  void* counts;
+  uint64_t* docs;
+  uint64_t* doc_ptr;
+  uint64_t* doc_len;
+  Slot* arena;
+  uint64_t total;
+};
+
+bool use_doc_kernel(const wc_opts* o) {
+  return o->mode == WC_PER_DOC && !(o->debug_flags & WC_DEBUG_DIRECT);
+}
+
+void layout_docs(uint64_t len, uint64_t n_docs, const wc_opts* o, void* ws, DocLayout* L) {
+  L->n_win = len / kMinWin + 1;  // room for any work-item size
+  L->cap_b = o->word_bytes_cap ? o->word_bytes_cap : std::max<uint64_t>(len / 4, 4096);
+  L->cap_e = L->cap_b / 3 + n_docs + 64;
+  L->arena_slots = o->table_slots ? o->table_slots
+                                  : std::max<uint64_t>(1ull << 16, len / 16 + 64 * 4096);
+  Bump B(ws);
+  L->hdr = B.take<Header>(sizeof(Header));
+  L->task = B.take<DocTask>(sizeof(DocTask));
+  L->win_doc = B.take<uint64_t>((L->n_win + 1) * 8);
+  L->woff = B.take<uint64_t>((L->cap_e + 1) * 8);
+  L->words = B.take<uint8_t>(L->cap_b);
+  L->counts = B.take<uint8_t>(L->cap_e * o->count_bytes);
+  L->docs = B.take<uint64_t>(L->cap_e * 8);
+  L->doc_ptr = B.take<uint64_t>(std::max<uint64_t>(n_docs, 1) * 8);
+  L->doc_len = B.take<uint64_t>(std::max<uint64_t>(n_docs, 1) * 8);
+  L->arena = B.take<Slot>(L->arena_slots * sizeof(Slot));
+  L->total = B.off;
+}
+
+DocParams doc_params(const DocLayout& L, const wc_opts* o, uint32_t lds, uint32_t pct,
+                     uint32_t chunk) {
+  DocParams P;
+  P.lds_cap = (uint32_t)((uint64_t)lds * (pct ? pct : 75) / 100);
+  if (P.lds_cap < 1) P.lds_cap = 1;
+  if (P.lds_cap > lds - lds / 8) P.lds_cap = lds - lds / 8;
+  P.pad0 = 0;
+  P.win_bytes = chunk;
+  P.task = L.task;
+  P.hdr = L.hdr;
+  P.win_doc = L.win_doc;
+  P.max_win = L.n_win;
+  P.word_offsets = L.woff;
+  P.words = L.words;
+  P.counts = L.counts;
+  P.count_bytes = o->count_bytes;
+  P.lds_entries = lds;
+  P.docs = L.docs;
+  P.doc_ptr = L.doc_ptr;
+  P.doc_len = L.doc_len;
+  P.cap_e = L.cap_e;
+  P.cap_b = L.cap_b;
+  P.arena = L.arena;
+  P.arena_slots = L.arena_slots;
+  P.key_mask = key_mask_of(o);
+  return P;
 }
 
 bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& tu,
@@ -154,12 +226,13 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
   L->woff = B.take<uint64_t>((S + 1) * 8);
   L->counts = B.take<uint8_t>(S * o->count_bytes);
   L->words = B.take<uint8_t>(L->word_cap);
-  L->docs = L->doc_ptr = L->list_docs = L->list_slots = L->sorted_docs = L->sorted_slots =
-      L->lens = nullptr;
+  L->docs = L->doc_ptr = L->doc_len = L->list_docs = L->list_slots = L->sorted_docs =
+      L->sorted_slots = L->lens = nullptr;
   L->cub = nullptr;
   if (per_doc) {
     L->docs = B.take<uint64_t>(S * 8);
     L->doc_ptr = B.take<uint64_t>((n_docs + 1) * 8);
+    L->doc_len = B.take<uint64_t>((n_docs + 1) * 8);
     L->list_docs = B.take<uint64_t>(S * 8);
     L->list_slots = B.take<uint64_t>(S * 8);
     L->sorted_docs = B.take<uint64_t>(S * 8);
@@ -220,6 +293,7 @@ hipError_t ensure_smem_attr() {
     hipError_t e = set_count_smem(512, 160 * 1024 - 40 * 1024);
     if (e == hipSuccess) e = set_count_smem(256, 160 * 1024 - 24 * 1024);
     if (e == hipSuccess) e = set_spill_smem(spill_count_dyn(kSpillLds), (size_t)kReduceLds * 20);
+    if (e == hipSuccess) e = set_doc_smem((size_t)kDocLds * 24);
     return e;
   }();
   return once;
@@ -258,6 +332,16 @@ wc_status wc_count_plan(uint64_t corpus_len, uint64_t n_docs, const wc_opts* opt
   Tune tu;
   if (!resolve_tuning(opts->tuning, &tu)) return WC_EINVAL;
   if (opts->mode == WC_PER_DOC && n_docs >= 0xffffffffull) return WC_EINVAL;
+  if (use_doc_kernel(opts)) {
+    if (corpus_len >= (1ull << 32)) return WC_EINVAL;  // packed output cursor: 32-bit fields
+    DocLayout D;
+    layout_docs(corpus_len, n_docs, opts, nullptr, &D);
+    out->table_slots = D.arena_slots;
+    out->workspace_bytes = D.total;
+    out->max_entries = D.cap_e;
+    out->word_bytes_cap = D.cap_b;
+    return WC_OK;
+  }
   CountLayout L;
   if (!layout_count(corpus_len, n_docs, opts, tu, nullptr, nullptr, &L)) return WC_EDEVICE;
   out->table_slots = L.S;
@@ -278,10 +362,55 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
   const bool per_doc = opts->mode == WC_PER_DOC;
   if (per_doc && n_docs >= 0xffffffffull) return WC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  HIPCHK(ensure_smem_attr());
+  if (use_doc_kernel(opts)) {
+    if (corpus_len >= (1ull << 32)) return WC_EINVAL;
+    DocLayout D;
+    layout_docs(corpus_len, n_docs, opts, d_workspace, &D);
+    if (D.total > workspace_bytes) return WC_ENOMEM;
+    uint32_t lds = opts->tuning && opts->tuning->lds_entries ? tu.lds : kDocLds;
+    Timer tm;
+    HIPCHK(tm.init(opts->debug_flags & WC_DEBUG_TIME));
+    if (tm.on) HIPCHK(hipEventRecord(tm.c, s));
+    DocTask task{d_corpus, corpus_len, d_offsets, n_docs};
+    HIPCHK(hipMemcpyAsync(D.task, &task, sizeof(task), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_fill_zero(D.hdr, sizeof(Header), s));
+    uint32_t grid = tu.grid ? tu.grid : (uint32_t)device_cus();
+    DocParams P = doc_params(D, opts, lds, tu.pct, tu.chunk);
+    if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
+    HIPCHK(launch_docs(P, grid, (size_t)lds * 24, s));
+    if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
+    Header h;
+    HIPCHK(hipMemcpyAsync(&h, D.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    memset(out, 0, sizeof(*out));
+    out->n_entries = h.out_cursor >> 32;
+    out->word_bytes = h.out_cursor & 0xffffffffull;
+    out->total_tokens = h.total_tokens;
+    out->n_docs = n_docs;
+    out->table_slots = std::max<uint64_t>(h.arena_next, D.arena_slots);
+    out->count_bytes = opts->count_bytes;
+    out->mode = WC_PER_DOC;
+    out->d_word_offsets = D.woff;
+    out->d_words = D.words;
+    out->d_counts = D.counts;
+    out->d_doc_ptr = D.doc_ptr;
+    out->d_doc_len = D.doc_len;
+    out->d_docs = D.docs;
+    if (tm.on) {
+      HIPCHK(hipEventRecord(tm.d, s));
+      HIPCHK(hipEventSynchronize(tm.d));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, tm.a, tm.b));
+      out->kernel_ms = ms;
+      HIPCHK(hipEventElapsedTime(&ms, tm.c, tm.d));
+      out->total_ms = ms;
+    }
+    return finish_flags(h);
+  }
   CountLayout L;
   if (!layout_count(corpus_len, n_docs, opts, tu, d_corpus, d_workspace, &L)) return WC_EDEVICE;
   if (L.total > workspace_bytes) return WC_ENOMEM;
-  HIPCHK(ensure_smem_attr());
 
   Timer tm;
   HIPCHK(tm.init(opts->debug_flags & WC_DEBUG_TIME));
@@ -403,7 +532,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
       HIPCHK(sort_pairs_u64(L.cub, &tb, L.list_docs, L.sorted_docs, L.list_slots, L.sorted_slots,
                             n, end_bit, s));
     }
-    HIPCHK(launch_doc_csr(L.sorted_docs, n, L.hdr, n_docs, L.doc_ptr, s));
+    HIPCHK(launch_doc_csr(L.sorted_docs, n, L.hdr, n_docs, L.doc_ptr, L.doc_len, s));
     HIPCHK(launch_slot_lens(L.table, L.sorted_slots, n, L.lens, s));
     size_t sb = L.scan_bytes;
     HIPCHK(excl_sum_u64(L.cub, &sb, L.lens, L.woff, n + 1, s));
@@ -420,6 +549,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
     HIPCHK(hipStreamSynchronize(s));
     h.word_bytes = wb;
     out->d_doc_ptr = L.doc_ptr;
+    out->d_doc_len = L.doc_len;
     out->d_docs = L.docs;
   }
   out->word_bytes = h.word_bytes;
@@ -738,12 +868,229 @@ wc_status wc_topk_ratio(const wc_result* const* corpora, uint32_t n_corpora, uin
   return WC_OK;
 }
 
+wc_status wc_table_to_host(const wc_result* t, uint64_t* word_offsets, uint8_t* words,
+                           void* counts) {
+  if (!t) return WC_EINVAL;
+  const uint64_t n = t->n_entries;
+  if (word_offsets && t->d_word_offsets)
+    HIPCHK(hipMemcpy(word_offsets, t->d_word_offsets, (n + 1) * 8, hipMemcpyDeviceToHost));
+  if (words && t->word_bytes) {
+    uint64_t b0 = 0;
+    HIPCHK(hipMemcpy(&b0, t->d_word_offsets, 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(words, t->d_words + b0, t->word_bytes, hipMemcpyDeviceToHost));
+  }
+  if (counts && n) HIPCHK(hipMemcpy(counts, t->d_counts, n * t->count_bytes, hipMemcpyDeviceToHost));
+  return WC_OK;
+}
+
 wc_status wc_hash_words(const uint8_t* d_bytes, const uint64_t* d_offsets, uint64_t n,
                         uint64_t* d_out, void* stream) {
   if (n && (!d_bytes || !d_offsets || !d_out)) return WC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(launch_hash_words(d_bytes, d_offsets, n, d_out, s));
   HIPCHK(hipStreamSynchronize(s));
+  return WC_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// batched per-document counting with a captured HIP graph
+// ------------------------------------------------------------------------------------------
+}  // extern "C"
+
+struct wc_batch {
+  wc_opts opts;
+  wc_tuning tuning;
+  uint64_t max_docs = 0, max_bytes = 0;
+  DocLayout D;
+  uint32_t lds = kDocLds, grid = 0;
+  DocTask* h_task = nullptr;  // pinned
+  Header* h_hdr = nullptr;    // pinned
+  hipStream_t bs = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+wc_status wc_batch_plan(const wc_opts* opts, uint64_t max_docs, uint64_t max_bytes,
+                        uint64_t* workspace_bytes) {
+  if (!opts_ok(opts) || !workspace_bytes || opts->mode != WC_PER_DOC) return WC_EINVAL;
+  if (max_bytes >= (1ull << 32)) return WC_EINVAL;
+  Tune tu;
+  if (!resolve_tuning(opts->tuning, &tu)) return WC_EINVAL;
+  DocLayout D;
+  layout_docs(max_bytes, max_docs, opts, nullptr, &D);
+  *workspace_bytes = D.total;
+  return WC_OK;
+}
+
+wc_status wc_batch_create(const wc_opts* opts, uint64_t max_docs, uint64_t max_bytes,
+                          void* d_workspace, uint64_t workspace_bytes, wc_batch** out) {
+  if (!out || !d_workspace) return WC_EINVAL;
+  uint64_t need = 0;
+  wc_status st = wc_batch_plan(opts, max_docs, max_bytes, &need);
+  if (st != WC_OK) return st;
+  if (workspace_bytes < need) return WC_ENOMEM;
+  Tune tu;
+  resolve_tuning(opts->tuning, &tu);
+  HIPCHK(ensure_smem_attr());
+  wc_batch* b = new wc_batch();
+  b->opts = *opts;
+  if (opts->tuning) {
+    b->tuning = *opts->tuning;
+    b->opts.tuning = &b->tuning;
+  }
+  b->max_docs = max_docs;
+  b->max_bytes = max_bytes;
+  layout_docs(max_bytes, max_docs, &b->opts, d_workspace, &b->D);
+  b->lds = opts->tuning && opts->tuning->lds_entries ? tu.lds : kDocLds;
+  b->grid = tu.grid ? tu.grid : (uint32_t)device_cus();
+  hipError_t e = hipHostMalloc((void**)&b->h_task, sizeof(DocTask), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_hdr, sizeof(Header), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    g_last_hip = (int32_t)e;
+    wc_batch_destroy(b);
+    return WC_EDEVICE;
+  }
+  *out = b;
+  return WC_OK;
+}
+
+wc_status wc_batch_run(wc_batch* b, const uint8_t* d_corpus, uint64_t corpus_len,
+                       const uint64_t* d_offsets, uint64_t n_docs, wc_result* out, void* stream) {
+  if (!b || !out || !d_offsets || (corpus_len && !d_corpus)) return WC_EINVAL;
+  if (corpus_len > b->max_bytes || n_docs > b->max_docs) return WC_EINVAL;
+  hipStream_t cs = (hipStream_t)stream;
+  // the caller's stream (where the corpus was produced) comes first
+  HIPCHK(hipEventRecord(b->ev, cs));
+  HIPCHK(hipStreamWaitEvent(b->bs, b->ev, 0));
+  *b->h_task = DocTask{d_corpus, corpus_len, d_offsets, n_docs};
+  if (!b->exec) {
+    HIPCHK(hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal));
+    Tune tu;
+    resolve_tuning(b->opts.tuning, &tu);
+    DocParams P = doc_params(b->D, &b->opts, b->lds, tu.pct, tu.chunk);
+    hipError_t e = hipMemcpyAsync(b->D.task, b->h_task, sizeof(DocTask), hipMemcpyHostToDevice,
+                                  b->bs);
+    if (e == hipSuccess) e = launch_fill_zero(b->D.hdr, sizeof(Header), b->bs);
+    if (e == hipSuccess) e = launch_docs(P, b->grid, (size_t)b->lds * 24, b->bs);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->h_hdr, b->D.hdr, sizeof(Header), hipMemcpyDeviceToHost, b->bs);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->bs, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      b->exec = nullptr;
+      g_last_hip = (int32_t)e;
+      return WC_EDEVICE;
+    }
+    b->graph = g;
+  }
+  HIPCHK(hipGraphLaunch(b->exec, b->bs));
+  HIPCHK(hipStreamSynchronize(b->bs));
+  const Header& h = *b->h_hdr;
+  memset(out, 0, sizeof(*out));
+  out->n_entries = h.out_cursor >> 32;
+  out->word_bytes = h.out_cursor & 0xffffffffull;
+  out->total_tokens = h.total_tokens;
+  out->n_docs = n_docs;
+  out->table_slots = std::max<uint64_t>(h.arena_next, b->D.arena_slots);
+  out->count_bytes = b->opts.count_bytes;
+  out->mode = WC_PER_DOC;
+  out->d_word_offsets = b->D.woff;
+  out->d_words = b->D.words;
+  out->d_counts = b->D.counts;
+  out->d_doc_ptr = b->D.doc_ptr;
+  out->d_doc_len = b->D.doc_len;
+  out->d_docs = b->D.docs;
+  return finish_flags(h);
+}
+
+wc_status wc_batch_destroy(wc_batch* b) {
+  if (!b) return WC_OK;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->ev) hipEventDestroy(b->ev);
+  if (b->bs) hipStreamDestroy(b->bs);
+  if (b->h_task) hipHostFree(b->h_task);
+  if (b->h_hdr) hipHostFree(b->h_hdr);
+  delete b;
+  return WC_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// autotuner
+// ------------------------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+std::vector<wc_tuning> tune_grid(const wc_opts* o) {
+  std::vector<wc_tuning> g;
+  if (o->mode == WC_PER_DOC) {
+    for (uint32_t chunk : {32u << 10, 64u << 10, 128u << 10})
+      for (uint32_t lds : {2048u, 4096u})
+        for (uint32_t pct : {60u, 85u}) g.push_back(wc_tuning{0, lds, 0, 0, pct, chunk});
+  } else {
+    for (uint32_t lds : {2048u, 4096u})
+      for (uint32_t pct : {60u, 75u, 90u}) g.push_back(wc_tuning{0, lds, 0, 0, pct, 0});
+  }
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+wc_status wc_autotune_plan(uint64_t len, uint64_t n_docs, const wc_opts* opts,
+                           uint64_t* workspace_bytes) {
+  if (!opts_ok(opts) || !workspace_bytes) return WC_EINVAL;
+  uint64_t need = 0;
+  for (const wc_tuning& t : tune_grid(opts)) {
+    wc_opts o = *opts;
+    o.tuning = &t;
+    wc_plan p;
+    wc_status st = wc_count_plan(len, n_docs, &o, &p);
+    if (st != WC_OK) return st;
+    need = std::max<uint64_t>(need, p.workspace_bytes);
+  }
+  *workspace_bytes = need;
+  return WC_OK;
+}
+
+wc_status wc_autotune(const uint8_t* d_sample, uint64_t len, const uint64_t* d_offsets,
+                      uint64_t n_docs, const wc_opts* opts, void* d_workspace,
+                      uint64_t workspace_bytes, wc_tuning* best, float* best_ms, void* stream) {
+  if (!best || !opts_ok(opts)) return WC_EINVAL;
+  float best_t = 3.4e38f;
+  bool found = false;
+  for (const wc_tuning& t : tune_grid(opts)) {
+    wc_opts o = *opts;
+    o.tuning = &t;
+    o.debug_flags |= WC_DEBUG_TIME;
+    float ms = 0;
+    wc_status st = WC_OK;
+    for (int rep = 0; rep < 3 && st == WC_OK; ++rep) {  // first run warms up
+      wc_result r;
+      st = wc_count(d_sample, len, d_offsets, n_docs, &o, d_workspace, workspace_bytes, &r,
+                    stream);
+      if (rep) ms += r.total_ms;
+    }
+    if (st == WC_EDEVICE) return st;
+    if (st != WC_OK) continue;  // a point that needs more room than planned is skipped
+    if (ms < best_t) {
+      best_t = ms;
+      *best = t;
+      found = true;
+    }
+  }
+  if (!found) return WC_ENOMEM;
+  if (best_ms) *best_ms = best_t / 2;
   return WC_OK;
 }
 

@@ -56,8 +56,10 @@ struct Header {
   uint64_t n_entries;
   uint64_t word_bytes;
   uint64_t max_count;
-  uint64_t work_next;     // work-queue cursor (batched launches)
-  uint64_t pad[9];
+  uint64_t work_next;     // work-queue cursor (persistent launches)
+  uint64_t out_cursor;    // per-document output: (entries << 32) | word bytes reserved
+  uint64_t arena_next;    // per-document output: private-table slots taken
+  uint64_t pad[7];
 };
 static_assert(sizeof(Header) == 128, "header layout");
 

@@ -62,6 +62,43 @@ hipError_t set_spill_smem(size_t count_dyn, size_t reduce_dyn);
 hipError_t launch_spill_count(const SpillParams& P, uint32_t grid, size_t dyn, hipStream_t s);
 hipError_t launch_spill_reduce(const SpillParams& P, size_t dyn, hipStream_t s);
 
+// per-document count (wc_docs.hip)
+constexpr uint64_t kWin = 64 * 1024;   // default bytes per work item window
+constexpr uint64_t kMinWin = 16 * 1024;
+constexpr uint32_t kDocW = 256;        // documents per sub-window
+constexpr uint32_t kDocLds = 4096;     // LDS table entries (24 bytes each)
+
+struct DocTask {           // device-resident: every size the per-document kernels read
+  const uint8_t* corpus;
+  uint64_t len;
+  const uint64_t* offsets;
+  uint64_t n_docs;
+};
+
+struct DocParams {
+  const DocTask* task;
+  Header* hdr;
+  uint64_t* win_doc;       // [max_win + 1]
+  uint64_t max_win;
+  uint64_t* word_offsets;  // [cap_e + 1]
+  uint8_t* words;          // [cap_b]
+  void* counts;
+  uint32_t count_bytes;
+  uint32_t lds_entries;
+  uint32_t lds_cap;        // live LDS entries before relief
+  uint32_t pad0;
+  uint64_t win_bytes;      // work item window
+  uint64_t* docs;          // [cap_e]
+  uint64_t* doc_ptr;       // [n_docs]
+  uint64_t* doc_len;       // [n_docs]
+  uint64_t cap_e, cap_b;
+  Slot* arena;             // private tables of large documents
+  uint64_t arena_slots;
+  uint64_t key_mask;
+};
+hipError_t set_doc_smem(size_t dyn);
+hipError_t launch_docs(const DocParams& P, uint32_t grid, size_t dyn, hipStream_t s);
+
 hipError_t launch_count(const CountParams& P, bool per_doc, uint32_t grid, uint32_t block,
                         size_t dyn, hipStream_t s);
 hipError_t set_count_smem(uint32_t block, size_t dyn);
@@ -106,7 +143,7 @@ hipError_t excl_sum_u64(void* temp, size_t* temp_bytes, const uint64_t* in, uint
 
 // per-document CSR: sort entries by document
 hipError_t launch_doc_csr(const uint64_t* docs_in, uint64_t n_entries_max, const Header* hdr,
-                          uint64_t n_docs, uint64_t* doc_ptr, hipStream_t s);
+                          uint64_t n_docs, uint64_t* doc_ptr, uint64_t* doc_len, hipStream_t s);
 
 // ---- fills ---------------------------------------------------------------------------------
 hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t s);

@@ -1,0 +1,553 @@
+// Serving: a request loop that counts texts as they arrive, keeps the resulting tables
+// resident on the device and answers merge queries (Section 3.3's summation of grouped counts,
+// across requests).
+//
+// Admission. The server owns one device pool of `mem_budget` bytes and sub-allocates from it
+// (first fit). A request is admitted when the memory its count needs (text, offsets,
+// workspace) is free; until then it waits in arrival order. Results are compacted into an
+// exact-size resident block, and the rest of the request's memory is returned at once.
+//
+// Continuous batching. `max_streams` worker threads each own a HIP stream (default priority),
+// so admitted requests run concurrently on the device. A worker that takes a small
+// single-document request also takes the small single-document requests queued right behind
+// it (up to kPackDocs requests / kPackBytes bytes) and counts them in one per-document launch,
+// then splits the per-document tables into one resident table per request.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "wc_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr uint32_t kPackDocs = 64;
+constexpr uint64_t kPackBytes = 4ull << 20;
+constexpr uint64_t kSmallBytes = 1ull << 20;
+constexpr uint64_t kPoolAlign = 256;
+
+// First-fit allocator over [0, size) of the device pool.
+class Pool {
+ public:
+  void init(uint8_t* base, uint64_t size) {
+    base_ = base;
+    free_[0] = size;
+  }
+  uint8_t* alloc(uint64_t bytes) {
+    bytes = (bytes + kPoolAlign - 1) & ~(kPoolAlign - 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        uint64_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_[off] = bytes;
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(uint8_t* p) {
+    if (!p) return;
+    uint64_t off = (uint64_t)(p - base_);
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    uint64_t len = u->second;
+    used_.erase(u);
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + len) {
+      len += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        pv->second += len;
+        return;
+      }
+    }
+    free_[off] = len;
+  }
+
+ private:
+  uint8_t* base_ = nullptr;
+  std::map<uint64_t, uint64_t> free_, used_;
+};
+
+struct Request {
+  uint64_t id = 0;
+  std::vector<uint8_t> text;      // host copy (host input)
+  const uint8_t* dev_text = nullptr;
+  uint64_t len = 0;
+  std::vector<uint64_t> offsets;
+  wc_opts opts{};
+  wc_tuning tuning{};
+  bool merge = false;
+  std::vector<uint64_t> merge_ids;
+  // state
+  int state = 0;  // 0 queued, 1 running, 2 done
+  wc_status status = WC_EAGAIN;
+  uint8_t* resident = nullptr;
+  wc_result res{};
+  double t_submit = 0, t_start = 0, t_done = 0;
+};
+
+double now_s() {
+  return std::chrono::duration<double>(Clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct wc_server {
+  int device = 0;
+  uint64_t budget = 0;
+  uint8_t* pool_mem = nullptr;
+  Pool pool;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done, cv_mem;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+  uint64_t next_id = 1;
+  uint32_t holders = 0;  // requests holding count memory
+  bool stop = false;
+  std::atomic<uint64_t> launches{0};
+};
+
+namespace {
+
+// compact a table (device arrays) into one resident block: [word_offsets | counts | words]
+wc_status keep_resident(wc_server* S, hipStream_t s, const wc_result& t, uint64_t e_begin,
+                        uint64_t n, Request* R) {
+  const uint32_t cb = t.count_bytes;
+  // word offsets of the kept entries (absolute in t) and their byte range
+  std::vector<uint64_t> woff(n + 1);
+  if (hipMemcpyAsync(woff.data(), t.d_word_offsets + e_begin, (n + 1) * 8,
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return WC_EDEVICE;
+  const uint64_t b0 = woff[0], nb = woff[n] - woff[0];
+  for (auto& x : woff) x -= b0;
+  const uint64_t bytes = (n + 1) * 8 + n * cb + nb + 64;
+  uint8_t* mem;
+  {
+    // never wait here (this worker still holds its count memory): a budget that resident
+    // tables have filled is reported as WC_ENOMEM for this request
+    std::lock_guard<std::mutex> lk(S->mu);
+    mem = S->pool.alloc(bytes);
+  }
+  if (!mem) return WC_ENOMEM;
+  uint64_t* d_off = (uint64_t*)mem;
+  uint8_t* d_cnt = mem + (((n + 1) * 8 + 15) & ~15ull);
+  uint8_t* d_words = d_cnt + ((n * cb + 15) & ~15ull);
+  hipError_t e = hipMemcpyAsync(d_off, woff.data(), (n + 1) * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n)
+    e = hipMemcpyAsync(d_cnt, (const uint8_t*)t.d_counts + e_begin * cb, n * cb,
+                       hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && nb)
+    e = hipMemcpyAsync(d_words, t.d_words + b0, nb, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->pool.release(mem);
+    return WC_EDEVICE;
+  }
+  R->resident = mem;
+  memset(&R->res, 0, sizeof(R->res));
+  R->res.n_entries = n;
+  R->res.word_bytes = nb;
+  R->res.count_bytes = cb;
+  R->res.mode = WC_GLOBAL;
+  R->res.n_docs = 1;
+  R->res.d_word_offsets = d_off;
+  R->res.d_words = d_words;
+  R->res.d_counts = d_cnt;
+  return WC_OK;
+}
+
+// Take count memory for a request, waiting while other requests hold count memory (they
+// will return it); when none does, the memory is held by resident tables, which only the
+// caller can release, so the request fails with WC_ENOMEM instead of waiting.
+uint8_t* pool_alloc_wait(wc_server* S, uint64_t bytes) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  uint8_t* p;
+  while (!(p = S->pool.alloc(bytes))) {
+    if (S->stop || S->holders == 0) return nullptr;
+    S->cv_mem.wait(lk);
+  }
+  ++S->holders;
+  return p;
+}
+
+void pool_free(wc_server* S, uint8_t* p) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->pool.release(p);
+  --S->holders;
+  S->cv_mem.notify_all();
+}
+
+void finish(wc_server* S, Request* R, wc_status st) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  R->status = st;
+  R->state = 2;
+  R->t_done = now_s();
+  R->text.clear();
+  R->text.shrink_to_fit();
+  S->cv_done.notify_all();
+}
+
+// Count a group of requests. One request: its own wc_count (its opts). Several small
+// single-document requests: one per-document count, split per request.
+void run_group(wc_server* S, hipStream_t s, std::vector<std::shared_ptr<Request>>& G) {
+  const double t0 = now_s();
+  for (auto& r : G) r->t_start = t0;
+  if (G.size() == 1 && G[0]->merge) {
+    Request* R = G[0].get();
+    // inputs were submitted before the merge, so they are running or done: wait for them
+    std::vector<const wc_result*> ins;
+    std::vector<std::shared_ptr<Request>> keep;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      for (uint64_t id : R->merge_ids) {
+        auto it = S->reqs.find(id);
+        if (it == S->reqs.end()) {
+          ins.clear();
+          break;
+        }
+        auto in = it->second;
+        S->cv_done.wait(lk, [&] { return in->state == 2; });
+        if (in->status != WC_OK) {
+          ins.clear();
+          break;
+        }
+        keep.push_back(in);
+        ins.push_back(&in->res);
+      }
+    }
+    if (ins.empty()) return finish(S, R, WC_EINVAL);
+    wc_opts o = R->opts;
+    wc_plan p;
+    wc_status st = wc_merge_plan(ins.data(), (uint32_t)ins.size(), &o, &p);
+    if (st != WC_OK) return finish(S, R, st);
+    uint8_t* ws = pool_alloc_wait(S, p.workspace_bytes);
+    if (!ws) return finish(S, R, WC_ENOMEM);
+    wc_result t;
+    st = wc_merge(ins.data(), (uint32_t)ins.size(), &o, ws, p.workspace_bytes, &t, s);
+    S->launches++;
+    if (st == WC_OK) st = keep_resident(S, s, t, 0, t.n_entries, R);
+    if (st == WC_OK) R->res.total_tokens = t.total_tokens;
+    pool_free(S, ws);
+    return finish(S, R, st);
+  }
+  // stage the texts on the device (one buffer for the group)
+  uint64_t total = 0;
+  for (auto& r : G) total += r->len;
+  const bool packed = G.size() > 1;
+  uint64_t n_docs_all = 0;
+  for (auto& r : G) n_docs_all += packed ? 1 : r->offsets.size() - 1;
+  wc_opts o = G[0]->opts;
+  if (packed) {
+    o.mode = WC_PER_DOC;
+    o.tuning = nullptr;
+    o.table_slots = 0;
+    o.word_bytes_cap = 0;
+  }
+  wc_status st = WC_OK;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    wc_plan p;
+    st = wc_count_plan(total, n_docs_all, &o, &p);
+    if (st != WC_OK) break;
+    const uint64_t off_bytes = (n_docs_all + 1) * 8;
+    const uint64_t need = p.workspace_bytes + ((total + 255) & ~255ull) + off_bytes + 512;
+    if (need > S->budget) {
+      st = WC_ENOMEM;
+      break;
+    }
+    uint8_t* mem = pool_alloc_wait(S, need);
+    if (!mem) {
+      st = WC_ENOMEM;
+      break;
+    }
+    uint8_t* d_text = mem;
+    uint64_t* d_off = (uint64_t*)(mem + ((total + 255) & ~255ull));
+    uint8_t* ws = (uint8_t*)d_off + ((off_bytes + 255) & ~255ull);
+    std::vector<uint64_t> off;
+    off.reserve(n_docs_all + 1);
+    uint64_t pos = 0;
+    hipError_t e = hipSuccess;
+    for (auto& r : G) {
+      if (r->dev_text) e = hipMemcpyAsync(d_text + pos, r->dev_text, r->len, hipMemcpyDeviceToDevice, s);
+      else if (r->len) e = hipMemcpyAsync(d_text + pos, r->text.data(), r->len, hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) break;
+      if (packed) {
+        off.push_back(pos);
+      } else {
+        for (size_t i = 0; i + 1 < r->offsets.size(); ++i) off.push_back(pos + r->offsets[i]);
+      }
+      pos += r->len;
+    }
+    if (packed) off.push_back(pos);
+    else off.push_back(pos - G[0]->len + G[0]->offsets.back());
+    if (e == hipSuccess) e = hipMemcpyAsync(d_off, off.data(), off_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      pool_free(S, mem);
+      st = WC_EDEVICE;
+      break;
+    }
+    wc_result t;
+    st = wc_count(d_text, total, d_off, n_docs_all, &o, ws, p.workspace_bytes, &t, s);
+    S->launches++;
+    if (st == WC_ETABLEFULL && o.mode == WC_GLOBAL) {
+      o.table_slots = 2 * p.table_slots;
+      pool_free(S, mem);
+      continue;
+    }
+    if (st == WC_ENOMEM && !(t.word_bytes <= p.word_bytes_cap && t.table_slots <= p.table_slots)) {
+      o.word_bytes_cap = std::max<uint64_t>(t.word_bytes, 3 * t.n_entries) * 5 / 4 + 4096;
+      if (o.mode == WC_PER_DOC && t.table_slots > p.table_slots) o.table_slots = 2 * t.table_slots;
+      pool_free(S, mem);
+      continue;
+    }
+    if (st == WC_OK) {
+      if (!packed) {
+        st = keep_resident(S, s, t, 0, t.n_entries, G[0].get());
+        if (st == WC_OK) G[0]->res.total_tokens = t.total_tokens;
+      } else {
+        std::vector<uint64_t> dptr(n_docs_all), dlen(n_docs_all);
+        e = hipMemcpyAsync(dptr.data(), t.d_doc_ptr, n_docs_all * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(dlen.data(), t.d_doc_len, n_docs_all * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = WC_EDEVICE;
+        for (size_t i = 0; st == WC_OK && i < G.size(); ++i) {
+          wc_status si = keep_resident(S, s, t, dptr[i], dlen[i], G[i].get());
+          if (si != WC_OK) st = si;
+        }
+        // token totals per request: sum of its counts (host side, from the resident table)
+        for (size_t i = 0; st == WC_OK && i < G.size(); ++i) {
+          Request* R = G[i].get();
+          uint64_t n = R->res.n_entries, sum = 0;
+          if (n) {
+            std::vector<int64_t> c8(n);
+            std::vector<int32_t> c4(n);
+            if (R->res.count_bytes == 4) {
+              e = hipMemcpyAsync(c4.data(), R->res.d_counts, n * 4, hipMemcpyDeviceToHost, s);
+            } else {
+              e = hipMemcpyAsync(c8.data(), R->res.d_counts, n * 8, hipMemcpyDeviceToHost, s);
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) { st = WC_EDEVICE; break; }
+            for (uint64_t j = 0; j < n; ++j) sum += R->res.count_bytes == 4 ? (uint64_t)c4[j] : (uint64_t)c8[j];
+          }
+          R->res.total_tokens = sum;
+        }
+      }
+    }
+    pool_free(S, mem);
+    break;
+  }
+  for (auto& r : G) finish(S, r.get(), st);
+}
+
+void worker(wc_server* S, int idx) {
+  hipSetDevice(S->device);
+  hipStream_t s = S->streams[idx];
+  while (true) {
+    std::vector<std::shared_ptr<Request>> G;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+      if (S->stop && S->queue.empty()) return;
+      auto first = S->queue.front();
+      S->queue.pop_front();
+      first->state = 1;
+      G.push_back(first);
+      auto small = [](const Request& r) {
+        return !r.merge && r.offsets.size() == 2 && r.offsets[0] == 0 && r.offsets[1] == r.len &&
+               r.len <= kSmallBytes;
+      };
+      if (small(*first)) {
+        uint64_t bytes = first->len;
+        while (!S->queue.empty() && G.size() < kPackDocs) {
+          auto& nx = S->queue.front();
+          if (!small(*nx) || bytes + nx->len > kPackBytes ||
+              nx->opts.count_bytes != first->opts.count_bytes ||
+              nx->opts.debug_hash_bits != first->opts.debug_hash_bits)
+            break;
+          bytes += nx->len;
+          nx->state = 1;
+          G.push_back(nx);
+          S->queue.pop_front();
+        }
+      }
+    }
+    run_group(S, s, G);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+wc_status wc_server_create(int device, uint64_t mem_budget, uint32_t max_streams,
+                           wc_server** out) {
+  if (!out || mem_budget < (1ull << 20) || max_streams == 0 || max_streams > 16) return WC_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return WC_EDEVICE;
+  wc_server* S = new wc_server();
+  S->device = device;
+  S->budget = mem_budget;
+  if (hipMalloc((void**)&S->pool_mem, mem_budget) != hipSuccess) {
+    delete S;
+    return WC_ENOMEM;
+  }
+  S->pool.init(S->pool_mem, mem_budget);
+  for (uint32_t i = 0; i < max_streams; ++i) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      for (auto x : S->streams) hipStreamDestroy(x);
+      hipFree(S->pool_mem);
+      delete S;
+      return WC_EDEVICE;
+    }
+    S->streams.push_back(s);
+  }
+  for (uint32_t i = 0; i < max_streams; ++i) S->workers.emplace_back(worker, S, (int)i);
+  *out = S;
+  return WC_OK;
+}
+
+wc_status wc_server_submit(wc_server* S, const uint8_t* text, uint64_t len,
+                           const uint64_t* offsets, uint64_t n_docs, int text_on_device,
+                           const wc_opts* opts, uint64_t* req_id) {
+  if (!S || !req_id || !opts || (len && !text) || !offsets) return WC_EINVAL;
+  if (opts->count_bytes != 4 && opts->count_bytes != 8) return WC_EINVAL;
+  if (opts->mode != WC_GLOBAL) return WC_EINVAL;  // per-request tables are global tables
+  for (uint64_t i = 0; i < n_docs; ++i)
+    if (offsets[i] > offsets[i + 1]) return WC_EINVAL;
+  if (offsets[n_docs] > len) return WC_EINVAL;
+  // admission test: the request must fit the budget on its own
+  wc_plan p;
+  wc_opts o = *opts;
+  o.tuning = nullptr;
+  wc_status st = wc_count_plan(len, n_docs, &o, &p);
+  if (st != WC_OK) return st;
+  if (p.workspace_bytes + len + (n_docs + 1) * 8 + 1024 > S->budget) return WC_ENOMEM;
+  auto R = std::make_shared<Request>();
+  R->len = len;
+  if (text_on_device) R->dev_text = text;
+  else R->text.assign(text, text + len);
+  R->offsets.assign(offsets, offsets + n_docs + 1);
+  R->opts = o;
+  R->t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    R->id = S->next_id++;
+    S->reqs[R->id] = R;
+    S->queue.push_back(R);
+    *req_id = R->id;
+  }
+  S->cv_work.notify_one();
+  return WC_OK;
+}
+
+wc_status wc_server_poll(wc_server* S, uint64_t id, wc_result* out) {
+  if (!S || !out) return WC_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(id);
+  if (it == S->reqs.end()) return WC_EINVAL;
+  if (it->second->state != 2) return WC_EAGAIN;
+  *out = it->second->res;
+  return it->second->status;
+}
+
+wc_status wc_server_wait(wc_server* S, uint64_t id, wc_result* out) {
+  if (!S || !out) return WC_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(id);
+  if (it == S->reqs.end()) return WC_EINVAL;
+  auto R = it->second;
+  S->cv_done.wait(lk, [&] { return R->state == 2; });
+  *out = R->res;
+  return R->status;
+}
+
+wc_status wc_server_times(wc_server* S, uint64_t id, double* submit_s, double* start_s,
+                          double* done_s) {
+  if (!S) return WC_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(id);
+  if (it == S->reqs.end()) return WC_EINVAL;
+  if (submit_s) *submit_s = it->second->t_submit;
+  if (start_s) *start_s = it->second->t_start;
+  if (done_s) *done_s = it->second->t_done;
+  return it->second->state == 2 ? WC_OK : WC_EAGAIN;
+}
+
+wc_status wc_server_merge(wc_server* S, const uint64_t* ids, uint32_t k, const wc_opts* opts,
+                          uint64_t* new_id) {
+  if (!S || !new_id || !ids || k == 0) return WC_EINVAL;
+  auto R = std::make_shared<Request>();
+  R->merge = true;
+  R->merge_ids.assign(ids, ids + k);
+  wc_opts o{};
+  o.count_bytes = opts ? opts->count_bytes : 8;
+  R->opts = o;
+  R->t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    R->id = S->next_id++;
+    S->reqs[R->id] = R;
+    S->queue.push_back(R);
+    *new_id = R->id;
+  }
+  S->cv_work.notify_one();
+  return WC_OK;
+}
+
+wc_status wc_server_release(wc_server* S, uint64_t id) {
+  if (!S) return WC_EINVAL;
+  std::shared_ptr<Request> R;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return WC_EINVAL;
+    R = it->second;
+    S->cv_done.wait(lk, [&] { return R->state == 2; });
+    S->reqs.erase(it);
+    if (R->resident) S->pool.release(R->resident);
+    R->resident = nullptr;
+    S->cv_mem.notify_all();
+  }
+  return WC_OK;
+}
+
+uint64_t wc_server_launches(wc_server* S) { return S ? S->launches.load() : 0; }
+
+wc_status wc_server_destroy(wc_server* S) {
+  if (!S) return WC_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  S->cv_mem.notify_all();
+  for (auto& t : S->workers) t.join();
+  for (auto s : S->streams) hipStreamDestroy(s);
+  hipFree(S->pool_mem);
+  delete S;
+  return WC_OK;
+}
+
+}  // extern "C"

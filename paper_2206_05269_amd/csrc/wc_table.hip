@@ -337,11 +337,19 @@ __global__ void doc_ptr_kernel(const uint64_t* docs_sorted, const Header* hdr, u
   for (uint64_t d = dprev; d <= dcur && d <= n_docs; ++d) doc_ptr[d] = e;
 }
 
+__global__ void doc_len_kernel(const uint64_t* doc_ptr, uint64_t n_docs, uint64_t* doc_len) {
+  uint64_t d = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (d < n_docs) doc_len[d] = doc_ptr[d + 1] - doc_ptr[d];
+}
+
 hipError_t launch_doc_csr(const uint64_t* docs_sorted, uint64_t n_entries_max, const Header* hdr,
-                          uint64_t n_docs, uint64_t* doc_ptr, hipStream_t s) {
+                          uint64_t n_docs, uint64_t* doc_ptr, uint64_t* doc_len, hipStream_t s) {
   uint32_t grid = (uint32_t)((n_entries_max + 1 + 255) / 256);
   hipLaunchKernelGGL(doc_ptr_kernel, dim3(grid), dim3(256), 0, s, docs_sorted, hdr, n_docs,
                      doc_ptr);
+  if (n_docs)
+    hipLaunchKernelGGL(doc_len_kernel, dim3((uint32_t)((n_docs + 255) / 256)), dim3(256), 0, s,
+                       doc_ptr, n_docs, doc_len);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@ when the library or a GPU is missing these functions raise.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
@@ -36,7 +37,7 @@ class WcError(RuntimeError):
 class Tuning(ctypes.Structure):
     _fields_ = [("stage_bytes", ctypes.c_uint32), ("lds_entries", ctypes.c_uint32),
                 ("flush_policy", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
-                ("lds_load_pct", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("lds_load_pct", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32)]
 
 
 class Opts(ctypes.Structure):
@@ -57,7 +58,8 @@ class Result(ctypes.Structure):
                 ("table_slots", ctypes.c_uint64), ("count_bytes", ctypes.c_uint32),
                 ("mode", ctypes.c_uint32), ("d_word_offsets", ctypes.c_void_p),
                 ("d_words", ctypes.c_void_p), ("d_counts", ctypes.c_void_p),
-                ("d_doc_ptr", ctypes.c_void_p), ("d_docs", ctypes.c_void_p),
+                ("d_doc_ptr", ctypes.c_void_p), ("d_doc_len", ctypes.c_void_p),
+                ("d_docs", ctypes.c_void_p),
                 ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
 
 
@@ -96,6 +98,37 @@ def lib():
         L.wc_topk_ratio.argtypes = [ctypes.POINTER(ctypes.POINTER(Result)), u32, u32, u64, vp,
                                     u64, ctypes.POINTER(TopKStruct), vp]
         L.wc_hash_words.argtypes = [vp, vp, u64, vp, vp]
+        L.wc_table_to_host.argtypes = [ctypes.POINTER(Result), vp, vp, vp]
+        L.wc_table_to_host.restype = ctypes.c_int32
+        L.wc_server_create.argtypes = [ctypes.c_int, u64, u32, ctypes.POINTER(vp)]
+        L.wc_server_submit.argtypes = [vp, vp, u64, vp, u64, ctypes.c_int, ctypes.POINTER(Opts),
+                                       ctypes.POINTER(u64)]
+        L.wc_server_poll.argtypes = [vp, u64, ctypes.POINTER(Result)]
+        L.wc_server_wait.argtypes = [vp, u64, ctypes.POINTER(Result)]
+        L.wc_server_times.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.wc_server_merge.argtypes = [vp, ctypes.POINTER(u64), u32, ctypes.POINTER(Opts),
+                                      ctypes.POINTER(u64)]
+        L.wc_server_release.argtypes = [vp, u64]
+        L.wc_server_launches.argtypes = [vp]
+        L.wc_server_launches.restype = u64
+        L.wc_server_destroy.argtypes = [vp]
+        for f in ("wc_server_create", "wc_server_submit", "wc_server_poll", "wc_server_wait",
+                  "wc_server_times", "wc_server_merge", "wc_server_release", "wc_server_destroy"):
+            getattr(L, f).restype = ctypes.c_int32
+        L.wc_autotune_plan.argtypes = [u64, u64, ctypes.POINTER(Opts), ctypes.POINTER(u64)]
+        L.wc_autotune.argtypes = [vp, u64, vp, u64, ctypes.POINTER(Opts), vp, u64,
+                                  ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float), vp]
+        L.wc_autotune_plan.restype = ctypes.c_int32
+        L.wc_autotune.restype = ctypes.c_int32
+        L.wc_batch_plan.argtypes = [ctypes.POINTER(Opts), u64, u64, ctypes.POINTER(u64)]
+        L.wc_batch_create.argtypes = [ctypes.POINTER(Opts), u64, u64, vp, u64,
+                                      ctypes.POINTER(vp)]
+        L.wc_batch_run.argtypes = [vp, vp, u64, vp, u64, ctypes.POINTER(Result), vp]
+        L.wc_batch_destroy.argtypes = [vp]
+        for f in ("wc_batch_plan", "wc_batch_create", "wc_batch_run", "wc_batch_destroy"):
+            getattr(L, f).restype = ctypes.c_int32
         for f in ("wc_count_plan", "wc_count", "wc_merge_plan", "wc_merge", "wc_topk_ratio_plan",
                   "wc_topk_ratio", "wc_hash_words"):
             getattr(L, f).restype = ctypes.c_int32
@@ -156,7 +189,12 @@ class Table:
     def doc_ptr(self) -> Optional[torch.Tensor]:
         if not self.res.d_doc_ptr:
             return None
-        return self._view(self.res.d_doc_ptr, 8 * (int(self.res.n_docs) + 1), torch.int64)
+        return self._view(self.res.d_doc_ptr, 8 * int(self.res.n_docs), torch.int64)
+
+    def doc_len(self) -> Optional[torch.Tensor]:
+        if not self.res.d_doc_len:
+            return None
+        return self._view(self.res.d_doc_len, 8 * int(self.res.n_docs), torch.int64)
 
     def docs(self) -> Optional[torch.Tensor]:
         if not self.res.d_docs:
@@ -195,8 +233,8 @@ def _opts(count_bytes, per_doc, table_slots, tuning, debug_flags, debug_hash_bit
 
 
 def make_tuning(stage_bytes=0, lds_entries=0, flush_policy=WC_FLUSH_ALL, grid_blocks=0,
-                lds_load_pct=0) -> Tuning:
-    return Tuning(stage_bytes, lds_entries, flush_policy, grid_blocks, lds_load_pct, 0)
+                lds_load_pct=0, chunk_bytes=0) -> Tuning:
+    return Tuning(stage_bytes, lds_entries, flush_policy, grid_blocks, lds_load_pct, chunk_bytes)
 
 
 def count_plan(corpus_len: int, n_docs: int, *, count_bytes=8, per_doc=False, table_slots=0,
@@ -244,10 +282,22 @@ def count(corpus: torch.Tensor, offsets: Optional[torch.Tensor] = None, *, count
                             ctypes.c_void_p(offsets.data_ptr()), n_docs, ctypes.byref(o),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(res),
                             _stream_handle(stream))
-        if st == WC_ETABLEFULL and regrow:
+        if st == WC_ETABLEFULL and regrow and not per_doc:
             table_slots = 2 * int(p.table_slots)
             continue
-        if st == WC_ENOMEM and regrow and res.word_bytes > p.word_bytes_cap:
+        if st == WC_ENOMEM and regrow and per_doc:
+            # per-document outputs or private tables ran out: grow what was short
+            need_b = max(int(res.word_bytes), 3 * int(res.n_entries))
+            grew = False
+            if need_b > p.word_bytes_cap or int(res.n_entries) > p.max_entries:
+                word_bytes_cap = need_b + need_b // 4 + 4096
+                grew = True
+            if int(res.table_slots) > p.table_slots:
+                table_slots = 2 * int(res.table_slots)
+                grew = True
+            if grew:
+                continue
+        if st == WC_ENOMEM and regrow and not per_doc and res.word_bytes > p.word_bytes_cap:
             word_bytes_cap = int(res.word_bytes)
             continue
         if st != WC_OK:
@@ -346,3 +396,200 @@ def hash_words(words: Sequence[bytes], device="cuda") -> list:
     if st != WC_OK:
         raise WcError(st, "wc_hash_words")
     return [int(x) & 0xFFFFFFFFFFFFFFFF for x in d_out[:len(words)].cpu().tolist()]
+
+
+class Batch:
+    """Per-document counting of whole corpora with one captured HIP graph (see wc_batch_*)."""
+
+    def __init__(self, max_docs: int, max_bytes: int, *, count_bytes: int = 4,
+                 tuning: Optional[Tuning] = None, word_bytes_cap: int = 0, table_slots: int = 0,
+                 device="cuda", debug_hash_bits: int = 0):
+        self._opts = _opts(count_bytes, True, table_slots, tuning, 0, debug_hash_bits,
+                           word_bytes_cap)
+        self._tuning = tuning  # keep the structure alive
+        need = ctypes.c_uint64()
+        st = lib().wc_batch_plan(ctypes.byref(self._opts), max_docs, max_bytes, ctypes.byref(need))
+        if st != WC_OK:
+            raise WcError(st, "wc_batch_plan")
+        self.workspace = _alloc(need.value, device)
+        h = ctypes.c_void_p()
+        st = lib().wc_batch_create(ctypes.byref(self._opts), max_docs, max_bytes,
+                                   ctypes.c_void_p(self.workspace.data_ptr()),
+                                   self.workspace.numel(), ctypes.byref(h))
+        if st != WC_OK:
+            raise WcError(st, "wc_batch_create")
+        self._h = h
+
+    def run(self, corpus: torch.Tensor, offsets: torch.Tensor, stream=None) -> Table:
+        _require_cuda(corpus, "corpus")
+        _require_cuda(offsets, "offsets")
+        res = Result()
+        st = lib().wc_batch_run(self._h, ctypes.c_void_p(corpus.data_ptr()), corpus.numel(),
+                                ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
+                                ctypes.byref(res), _stream_handle(stream))
+        if st != WC_OK:
+            raise WcError(st, "wc_batch_run")
+        return Table(res, self.workspace)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def result_to_dict(res: Result) -> dict:
+    """{word: count} of a table anywhere in device memory (copied with wc_table_to_host)."""
+    n = int(res.n_entries)
+    off = np.zeros(n + 1, dtype=np.uint64)
+    words = np.zeros(max(int(res.word_bytes), 1), dtype=np.uint8)
+    cnt = np.zeros(max(n, 1), dtype=np.int32 if res.count_bytes == 4 else np.int64)
+    st = lib().wc_table_to_host(ctypes.byref(res), off.ctypes.data_as(ctypes.c_void_p),
+                                words.ctypes.data_as(ctypes.c_void_p),
+                                cnt.ctypes.data_as(ctypes.c_void_p))
+    if st != WC_OK:
+        raise WcError(st, "wc_table_to_host")
+    off = off - off[0]
+    wb = words.tobytes()
+    return {wb[int(off[e]):int(off[e + 1])]: int(cnt[e]) for e in range(n)}
+
+
+class Server:
+    """Request server (see wc_server_* in include/wc.h): counts submitted texts on several
+    streams, keeps the tables resident, answers merge queries."""
+
+    def __init__(self, mem_budget: int, max_streams: int = 4, device: int = 0):
+        h = ctypes.c_void_p()
+        st = lib().wc_server_create(device, mem_budget, max_streams, ctypes.byref(h))
+        if st != WC_OK:
+            raise WcError(st, "wc_server_create")
+        self._h = h
+
+    def submit(self, text, offsets=None, *, count_bytes: int = 8) -> int:
+        """text: bytes / uint8 numpy array (host, copied) or a CUDA uint8 tensor (must stay
+        alive until the request completes)."""
+        on_dev = isinstance(text, torch.Tensor) and text.is_cuda
+        if on_dev:
+            n = text.numel()
+            ptr = ctypes.c_void_p(text.data_ptr())
+            keep = None
+        else:
+            buf = np.frombuffer(bytes(text), dtype=np.uint8) if isinstance(text, (bytes, bytearray)) \
+                else np.ascontiguousarray(text, dtype=np.uint8)
+            n = len(buf)
+            keep = buf if n else np.zeros(1, np.uint8)
+            ptr = keep.ctypes.data_as(ctypes.c_void_p)
+        off = np.ascontiguousarray([0, n] if offsets is None else offsets, dtype=np.uint64)
+        o = _opts(count_bytes, False, 0, None, 0, 0, 0)
+        rid = ctypes.c_uint64()
+        st = lib().wc_server_submit(self._h, ptr, n, off.ctypes.data_as(ctypes.c_void_p),
+                                    len(off) - 1, 1 if on_dev else 0, ctypes.byref(o),
+                                    ctypes.byref(rid))
+        if st != WC_OK:
+            raise WcError(st, "wc_server_submit")
+        return int(rid.value)
+
+    def poll(self, rid: int):
+        res = Result()
+        st = lib().wc_server_poll(self._h, rid, ctypes.byref(res))
+        return st, res
+
+    def wait(self, rid: int) -> Result:
+        res = Result()
+        st = lib().wc_server_wait(self._h, rid, ctypes.byref(res))
+        if st != WC_OK:
+            raise WcError(st, "wc_server_wait")
+        return res
+
+    def times(self, rid: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib().wc_server_times(self._h, rid, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return a.value, b.value, c.value
+
+    def merge(self, ids, *, count_bytes: int = 8) -> int:
+        arr = (ctypes.c_uint64 * len(ids))(*ids)
+        o = _opts(count_bytes, False, 0, None, 0, 0, 0)
+        rid = ctypes.c_uint64()
+        st = lib().wc_server_merge(self._h, arr, len(ids), ctypes.byref(o), ctypes.byref(rid))
+        if st != WC_OK:
+            raise WcError(st, "wc_server_merge")
+        return int(rid.value)
+
+    def release(self, rid: int):
+        lib().wc_server_release(self._h, rid)
+
+    def launches(self) -> int:
+        return int(lib().wc_server_launches(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _cache_file(path: Optional[str]) -> str:
+    if path:
+        return path
+    env = os.environ.get("WC_AUTOTUNE_CACHE")
+    if env:
+        return env
+    base = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(base, "wc_mi355x", "autotune.json")
+
+
+def autotune(corpus: torch.Tensor, offsets: torch.Tensor, *, per_doc: bool = True,
+             count_bytes: int = 4, cache_path: Optional[str] = None, use_cache: bool = True,
+             stream=None) -> Tuning:
+    """Pick a tuning for corpora like `corpus` by timing the library's candidate grid on it
+    (wc_autotune), caching the choice in a JSON file keyed by device, mode and sample size."""
+    _require_cuda(corpus, "corpus")
+    props = torch.cuda.get_device_properties(corpus.device)
+    size_class = int(corpus.numel()).bit_length()
+    key = f"{props.name}|{props.multi_processor_count}|{'doc' if per_doc else 'global'}|{size_class}"
+    path = _cache_file(cache_path)
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            return Tuning(*cache[key]["tuning"])
+    n_docs = offsets.numel() - 1
+    o = _opts(count_bytes, per_doc, 0, None, 0, 0, 0)
+    need = ctypes.c_uint64()
+    st = lib().wc_autotune_plan(corpus.numel(), n_docs, ctypes.byref(o), ctypes.byref(need))
+    if st != WC_OK:
+        raise WcError(st, "wc_autotune_plan")
+    ws = _alloc(need.value, corpus.device)
+    best = Tuning()
+    ms = ctypes.c_float()
+    st = lib().wc_autotune(ctypes.c_void_p(corpus.data_ptr()), corpus.numel(),
+                           ctypes.c_void_p(offsets.data_ptr()), n_docs, ctypes.byref(o),
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(best),
+                           ctypes.byref(ms), _stream_handle(stream))
+    if st != WC_OK:
+        raise WcError(st, "wc_autotune")
+    if use_cache:
+        cache[key] = {"tuning": [best.stage_bytes, best.lds_entries, best.flush_policy,
+                                 best.grid_blocks, best.lds_load_pct, best.chunk_bytes],
+                      "ms": ms.value}
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return best

@@ -59,13 +59,29 @@ def check(text, offsets=None, per_doc=False, **kw):
         wrong = [(k, g[k], w[k]) for k in w if k in g and g[k] != w[k]][:5]
         raise AssertionError(f"mismatch: missing {missing} extra {extra} wrong {wrong}")
     if per_doc:
-        dp = got.doc_ptr().cpu().numpy()
-        docs = got.docs().cpu().numpy()
-        n_docs = len(offsets) - 1
-        assert len(dp) == n_docs + 1 and dp[0] == 0 and dp[-1] == got.n_entries
-        for d in range(n_docs):
-            assert (docs[dp[d]:dp[d + 1]] == d).all()
+        check_doc_layout(got, len(offsets) - 1)
     return got
+
+
+def check_doc_layout(got, n_docs):
+    """Each document's entries are the doc_len[d] entries from doc_ptr[d]; they tile the
+    output exactly once; d_docs agrees; the word offsets are a CSR over the whole output."""
+    dp = got.doc_ptr().cpu().numpy()
+    dl = got.doc_len().cpu().numpy()
+    docs = got.docs().cpu().numpy()
+    n = got.n_entries
+    assert len(dp) == n_docs and len(dl) == n_docs
+    assert int(dl.sum()) == n
+    cover = np.zeros(n + 1, dtype=np.int64)
+    nz = dl > 0
+    np.add.at(cover, dp[nz], 1)
+    np.add.at(cover, dp[nz] + dl[nz], -1)
+    assert (np.cumsum(cover)[:n] == 1).all()
+    want_docs = np.repeat(np.arange(n_docs)[nz], dl[nz])
+    order = np.repeat(dp[nz], dl[nz]) + (np.arange(n) - np.repeat(np.cumsum(dl[nz]) - dl[nz], dl[nz]))
+    assert (docs[order] == want_docs).all()
+    wo = got.word_offsets().cpu().numpy()
+    assert wo[0] == 0 and (np.diff(wo) > 0).all() and wo[-1] == got.res.word_bytes
 
 
 PATHS = {"direct": wc.WC_DEBUG_DIRECT, "spill": wc.WC_DEBUG_SPILL}
@@ -267,6 +283,41 @@ def test_spill_tuning_points(lds, grid, pct):
     check(cs[0].text.numpy(), cs[0].offsets.numpy(), tuning=tu, debug_flags=wc.WC_DEBUG_SPILL)
 
 
+@pytest.mark.parametrize("lds", [256, 1024, 4096])
+def test_per_doc_relief_and_private_tables(lds):
+    """Documents larger than the LDS table (emission of complete documents, moves to private
+    tables), many tiny documents (several sub-windows per item), empty documents."""
+    tu = wc.make_tuning(lds_entries=lds)
+    c = synth.generate("plain-1MB")
+    big = c.text.numpy()[:600_000]
+    check(big, [0, 10, 10, 250_000, 250_001, 600_000], per_doc=True, tuning=tu)
+    tiny = synth.random_text(120_000, 9, alphabet=b"abcAB '. ")
+    off = np.arange(0, 120_001, 7)
+    off[-1] = 120_000
+    check(tiny, off, per_doc=True, tuning=tu)
+    check(b"", [0, 0, 0], per_doc=True, tuning=tu)
+
+
+def test_per_doc_long_words_and_collisions():
+    w = b"Z" * 40
+    docs = [w + b" " + w.lower(), b"a" * 17 + b" x", b"", w + b" y " * 3000]
+    text, off = join_docs(docs)
+    for bits in (0, 3):
+        check(text, off, per_doc=True, debug_hash_bits=bits)
+        check(text, off, per_doc=True, debug_hash_bits=bits, tuning=wc.make_tuning(lds_entries=256))
+
+
+def test_per_doc_direct_path_agrees():
+    c = synth.generate("batched-100k", scale=0.001)
+    check(c.text.numpy(), c.offsets.numpy(), per_doc=True, debug_flags=wc.WC_DEBUG_DIRECT)
+
+
+def test_per_doc_output_growth():
+    c = synth.generate("batched-100k", scale=0.001)
+    check(c.text.numpy(), c.offsets.numpy(), per_doc=True, word_bytes_cap=64, table_slots=4096,
+          tuning=wc.make_tuning(lds_entries=256))
+
+
 def test_spill_heavy_counts():
     """Records with counts above one (evictions, final flushes) and counts above 32767."""
     rng = np.random.default_rng(5)
@@ -387,3 +438,131 @@ def test_fnv1a_published_vectors():
     assert h == [0xcbf29ce484222325, 0xaf63dc4c8601ec8c, 0x85944171f73967e8]
     # folding: the hash is taken over folded bytes
     assert wc.hash_words([b"FooBar"]) == [0x85944171f73967e8]
+
+
+# ------------------------------------------------------------------------------------------
+# batched (captured graph)
+# ------------------------------------------------------------------------------------------
+
+def test_batch_graph_replays_match_oracle():
+    """One graph, replayed on corpora of different shapes, with eager work in between."""
+    b = wc.Batch(max_docs=20_000, max_bytes=8 << 20, count_bytes=4)
+    cases = []
+    c = synth.generate("batched-100k", scale=0.002)
+    cases.append((c.text.numpy(), c.offsets.numpy()))
+    t2 = synth.random_text(200_000, 3, alphabet=b"abAB '.xyz")
+    cases.append((np.frombuffer(t2, np.uint8), synth.random_splits(len(t2), 700, 4)))
+    cases.append((c.text.numpy()[:100_000], np.array([0, 5, 5, 60_000, 100_000])))
+    for rep in range(2):
+        for text, off in cases:
+            want = oracle.count(text, off, per_doc=True)
+            t, o = to_dev(text, off)
+            got = b.run(t, o)
+            assert got.total_tokens == want.total
+            assert got.as_dict() == want.as_dict()
+            check_doc_layout(got, len(off) - 1)
+            # unrelated eager work between replays
+            torch.cuda.synchronize()
+            _ = (t.float().sum() + 1).item()
+    b.close()
+
+
+def test_batch_rejects_oversize():
+    b = wc.Batch(max_docs=10, max_bytes=1000)
+    t, o = to_dev(b"x" * 2000, [0, 2000])
+    with pytest.raises(wc.WcError) as e:
+        b.run(t, o)
+    assert e.value.status == wc.WC_EINVAL
+    b.close()
+
+
+# ------------------------------------------------------------------------------------------
+# serving
+# ------------------------------------------------------------------------------------------
+
+def _requests(n, seed):
+    rng = np.random.default_rng(seed)
+    c = synth.generate("plain-1MB")
+    base = c.text.numpy()
+    out = []
+    for i in range(n):
+        size = int(min(len(base) - 1, np.exp(rng.normal(np.log(20_000), 1.5))))
+        a = int(rng.integers(0, len(base) - size))
+        out.append(base[a:a + size].tobytes())
+    return out
+
+
+def test_server_results_match_oracle_and_merge():
+    srv = wc.Server(mem_budget=256 << 20, max_streams=3)
+    texts = _requests(40, 1)
+    ids = [srv.submit(t) for t in texts]
+    for t, i in zip(texts, ids):
+        got = wc.result_to_dict(srv.wait(i))
+        assert got == oracle.count(t).as_dict()
+    m = srv.merge(ids[:10])
+    want = oracle.count(b"".join(texts[:10]), np.cumsum([0] + [len(t) for t in texts[:10]]))
+    assert wc.result_to_dict(srv.wait(m)) == want.as_dict()
+    assert srv.launches() < len(ids) + 1  # small requests were packed
+    for i in ids + [m]:
+        srv.release(i)
+    srv.close()
+
+
+def test_server_alone_and_in_the_mix_are_identical():
+    texts = _requests(60, 2)
+    probe = texts[17]
+    alone = wc.Server(mem_budget=128 << 20, max_streams=1)
+    a = wc.result_to_dict(alone.wait(alone.submit(probe)))
+    alone.close()
+    mix = wc.Server(mem_budget=64 << 20, max_streams=4)   # small budget: admission waits
+    ids = [mix.submit(t) for t in texts]
+    b = wc.result_to_dict(mix.wait(ids[17]))
+    assert a == b == oracle.count(probe).as_dict()
+    for t, i in zip(texts, ids):
+        assert wc.result_to_dict(mix.wait(i)) == oracle.count(t).as_dict()
+    mix.close()
+
+
+def test_server_budget_errors():
+    srv = wc.Server(mem_budget=4 << 20, max_streams=1)
+    with pytest.raises(wc.WcError) as e:
+        srv.submit(b"word " * 2_000_000)   # 10 MB text: larger than the budget
+    assert e.value.status == wc.WC_ENOMEM
+    i = srv.submit(b"a b c a")
+    assert wc.result_to_dict(srv.wait(i)) == {b"a": 2, b"b": 1, b"c": 1}
+    srv.close()
+
+
+def test_server_device_input():
+    c = synth.generate("plain-1MB")
+    t = c.text.to(DEV)
+    srv = wc.Server(mem_budget=256 << 20, max_streams=2)
+    i = srv.submit(t, c.offsets.numpy())
+    assert wc.result_to_dict(srv.wait(i)) == c.expected_table()
+    srv.close()
+
+
+def test_autotune_choice_is_exact_and_cached(tmp_path):
+    c = synth.generate("batched-100k", scale=0.002)
+    t, o = to_dev(c.text.numpy(), c.offsets.numpy())
+    cache = str(tmp_path / "tune.json")
+    tu = wc.autotune(t, o, per_doc=True, cache_path=cache)
+    assert tu.lds_entries in (2048, 4096) and tu.chunk_bytes in (32 << 10, 64 << 10, 128 << 10)
+    assert os.path.exists(cache)
+    tu2 = wc.autotune(t, o, per_doc=True, cache_path=cache)
+    assert (tu2.lds_entries, tu2.chunk_bytes, tu2.lds_load_pct) == \
+        (tu.lds_entries, tu.chunk_bytes, tu.lds_load_pct)
+    check(c.text.numpy(), c.offsets.numpy(), per_doc=True, tuning=tu)
+    b = wc.Batch(max_docs=len(c.offsets), max_bytes=len(c.text), tuning=tu)
+    got = b.run(t, o)
+    assert got.as_dict() == oracle.count(c.text.numpy(), c.offsets.numpy(), per_doc=True).as_dict()
+    b.close()
+    g = wc.autotune(t, o, per_doc=False, cache_path=cache)
+    check(c.text.numpy(), c.offsets.numpy(), tuning=g, debug_flags=wc.WC_DEBUG_SPILL)
+
+
+@pytest.mark.parametrize("chunk", [16 << 10, 32 << 10, 256 << 10, 1 << 20])
+def test_per_doc_chunk_sizes(chunk):
+    c = synth.generate("batched-100k", scale=0.002)
+    check(c.text.numpy(), c.offsets.numpy(), per_doc=True,
+          tuning=wc.make_tuning(chunk_bytes=chunk, lds_load_pct=50))
