@@ -52,8 +52,21 @@ def main():
     ap.add_argument("--cpu-sample-mb", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--plain-docs", type=int, default=2000)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device once (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        x = torch.ones(args.copy_probe << 20, dtype=torch.uint8, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"copied {x.numel()} bytes")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the counter would shard)", file=sys.stderr)
@@ -137,7 +150,84 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_docs_per_s(args.steps, args.warmup, args.plain_docs)
+    if not args.no_serving:
+        out["serving"] = serving(args.requests)
     print(json.dumps(out), flush=True)
+
+
+def serving(n_requests: int):
+    """Workload "serving": requests of lognormal size (median 256 KiB, sigma 2, clipped to
+    1 KiB..64 MiB) cut from Zipf(1.05) text over a 500,000-word vocabulary, submitted from host
+    memory to a server with a 1 GiB device budget and 4 streams. Arrivals are Poisson at 70%
+    of the capacity measured with all requests queued at once. Latency = completion - arrival."""
+    import threading
+    import numpy as np
+    import torch
+    from paper_2206_05269_amd import synth, wc
+    w = synth.WORKLOADS["serving"]
+    rng = np.random.default_rng(w.seed + 31)
+    sizes = synth.lognormal_sizes(n_requests, *w.lognormal, seed=w.seed + 7919)
+    total = int(sizes.sum())
+    log(f"generating {total} bytes of serving text on the GPU")
+    vocab, vlens = synth.make_vocab(w.vocab, w.max_len, w.seed)
+    c = synth.gen_stream(total, vocab, vlens, synth.zipf_probs(w.vocab, w.zipf_s), w.seed + 1,
+                         "cuda:0")
+    host = c.text.cpu().numpy()
+    del c
+    torch.cuda.empty_cache()
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    reqs = [host[a:a + n] for a, n in zip(starts, sizes)]
+    budget = 1 << 30
+
+    def run(rate):
+        srv = wc.Server(mem_budget=budget, max_streams=4)
+        ids, t_sub = [], []
+        gaps = rng.exponential(1.0 / rate, size=len(reqs)) if rate else np.zeros(len(reqs))
+        t0 = time.perf_counter()
+        next_t = t0
+        for r, g in zip(reqs, gaps):
+            next_t += g
+            d = next_t - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ids.append(srv.submit(r, count_bytes=8))
+        for i in ids:
+            srv.wait(i)
+        lat = []
+        first, last = float("inf"), 0.0
+        for i in ids:
+            a, _, b = srv.times(i)
+            lat.append(b - a)
+            first, last = min(first, a), max(last, b)
+        launches = srv.launches()
+        srv.close()
+        return np.array(lat), last - first, launches
+
+    run(0)  # warm-up
+    lat0, span0, _ = run(0)
+    cap = len(reqs) / span0
+    rate = 0.7 * cap
+    lat, span, launches = run(rate)
+    # plain: one synchronous upload + wc_count per request, one after another
+    m = min(len(reqs), 200)
+    t0 = time.perf_counter()
+    for r in reqs[:m]:
+        t = torch.from_numpy(r).to("cuda:0")
+        wc.count(t, count_bytes=8)
+    torch.cuda.synchronize()
+    plain_rps = m / (time.perf_counter() - t0)
+    res = {"workload": "serving", "requests": len(reqs), "bytes": total,
+           "budget_bytes": budget, "streams": 4, "capacity_req_per_s": round(cap, 1),
+           "offered_req_per_s": round(rate, 1),
+           "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+           "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+           "served_req_per_s": round(len(reqs) / span, 1),
+           "aggregate_GBps": round(total / span / 1e9, 3),
+           "launches": int(launches), "plain_req_per_s": round(plain_rps, 1),
+           "input": "host (pageable) memory; PCIe transfer included"}
+    log(f"serving p50 {res['p50_ms']} ms p99 {res['p99_ms']} ms, {res['served_req_per_s']} req/s "
+        f"vs plain {res['plain_req_per_s']} req/s")
+    return res
 
 
 def batched_docs_per_s(steps: int, warmup: int, plain_docs: int):

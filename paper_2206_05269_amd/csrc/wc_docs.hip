@@ -150,7 +150,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   __shared__ uint32_t s_pslots[kDocW];
   __shared__ uint32_t s_need[kDocW];        // a token of this document found no LDS slot
   __shared__ uint32_t s_live, s_carry[2], s_next_w;
-  __shared__ uint64_t s_item, s_e0, s_b0, s_tokens;
+  __shared__ uint64_t s_item, s_e0, s_b0, s_tokens, s_minpos;
   __shared__ uint32_t s_emitted, s_scan_tmp[NWAVE];
   extern __shared__ __align__(16) uint8_t s_dyn[];
   uint16_t* s_starts = (uint16_t*)s_buf;
@@ -318,8 +318,13 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
     for (uint32_t r = 0; r < nd; ++r) {
       if (!s_need[r] || s_pbase[r] != ~0ull) continue;
       if (tid == 0) {
+        // a document of b bytes has at most b/2 + 1 distinct words: b + 2 slots keep a small
+        // document's table at most half full; large documents get b/16 slots (natural text
+        // has far fewer distinct words than tokens)
         uint64_t bytes = s_doff[r + 1] - s_doff[r];
         uint64_t want = bytes / 16 > 4096 ? bytes / 16 : 4096;
+        if (bytes + 2 < want) want = bytes + 2;
+        if (want < 64) want = 64;
         uint64_t slots = 1;
         while (slots < want) slots <<= 1;
         uint64_t base = atomicAdd((unsigned long long*)&hdr->arena_next, (unsigned long long)slots);
@@ -614,7 +619,14 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
             // LDS entries, and every document with a waiting token, to a private table; after
             // that every waiting token has a place, so the loop ends.
             while (__syncthreads_or(pending)) {
-              const uint64_t first_pos = (uint64_t)(ls + s_starts[t0]);
+              // every token before the first waiting one is counted, so documents that end
+              // at or before that token's position are complete
+              if (tid == 0) s_minpos = ~0ull;
+              __syncthreads();
+              if (pending) atomicMin((unsigned long long*)&s_minpos,
+                                     (unsigned long long)(ls + s_starts[t]));
+              __syncthreads();
+              const uint64_t first_pos = s_minpos;
               const uint32_t em = s_emitted;
               uint32_t done = em;
               while (done < nd && s_doff[done + 1] <= first_pos) ++done;

@@ -316,7 +316,11 @@ void run_group(wc_server* S, hipStream_t s, std::vector<std::shared_ptr<Request>
     }
     if (st == WC_ENOMEM && !(t.word_bytes <= p.word_bytes_cap && t.table_slots <= p.table_slots)) {
       o.word_bytes_cap = std::max<uint64_t>(t.word_bytes, 3 * t.n_entries) * 5 / 4 + 4096;
-      if (o.mode == WC_PER_DOC && t.table_slots > p.table_slots) o.table_slots = 2 * t.table_slots;
+      if (o.mode == WC_PER_DOC && t.table_slots > p.table_slots) {
+        uint64_t want = 1;
+        while (want < 2 * t.table_slots) want <<= 1;
+        o.table_slots = want;
+      }
       pool_free(S, mem);
       continue;
     }

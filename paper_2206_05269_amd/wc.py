@@ -293,7 +293,7 @@ def count(corpus: torch.Tensor, offsets: Optional[torch.Tensor] = None, *, count
                 word_bytes_cap = need_b + need_b // 4 + 4096
                 grew = True
             if int(res.table_slots) > p.table_slots:
-                table_slots = 2 * int(res.table_slots)
+                table_slots = 1 << (2 * int(res.table_slots) - 1).bit_length()
                 grew = True
             if grew:
                 continue
