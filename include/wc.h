@@ -265,7 +265,9 @@ wc_status wc_server_destroy(wc_server* s);
  * point of a small grid of launch tunings (per-document mode: work-item bytes x LDS entries x
  * relief load; global mode: LDS entries x load) with HIP events on `stream`, and return the
  * fastest in *best (its time per call in *best_ms). The workspace must hold
- * wc_autotune_plan() bytes. The sample's counts are not returned. */
+ * wc_autotune_plan() bytes. The sample's counts are not returned. Output and private-table
+ * sizes come from opts (word_bytes_cap, table_slots) as in wc_count; a grid point that runs
+ * out of that room is skipped, and WC_ENOMEM is returned when no point fits. */
 wc_status wc_autotune_plan(uint64_t len, uint64_t n_docs, const wc_opts* opts,
                            uint64_t* workspace_bytes);
 wc_status wc_autotune(const uint8_t* d_sample, uint64_t len, const uint64_t* d_offsets,

@@ -313,9 +313,11 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   };
 
   // ---- move documents to private tables (all threads); their LDS entries go along ----------
-  auto convert = [&](uint32_t nd) {
+  // Documents before `em` are already emitted: a flag left on one of them from a token that
+  // later found an LDS slot is ignored.
+  auto convert = [&](uint32_t em, uint32_t nd) {
     // allocate and clear private tables for flagged documents
-    for (uint32_t r = 0; r < nd; ++r) {
+    for (uint32_t r = em; r < nd; ++r) {
       if (!s_need[r] || s_pbase[r] != ~0ull) continue;
       if (tid == 0) {
         // a document of b bytes has at most b/2 + 1 distinct words: b + 2 slots keep a small
@@ -643,7 +645,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
                   }
                 }
                 __syncthreads();
-                convert(nd);
+                convert(em, nd);
               }
               if (pending && place()) pending = false;
             }

@@ -568,7 +568,14 @@ def autotune(corpus: torch.Tensor, offsets: torch.Tensor, *, per_doc: bool = Tru
         if key in cache:
             return Tuning(*cache[key]["tuning"])
     n_docs = offsets.numel() - 1
-    o = _opts(count_bytes, per_doc, 0, None, 0, 0, 0)
+    # Size the outputs once: the counts (hence the output words) do not depend on the tuning;
+    # the private-table arena does, so it gets twice what a default-tuned count used. Grid
+    # points that still run out of room are skipped by the library.
+    sizing = count(corpus, offsets, count_bytes=count_bytes, per_doc=per_doc, stream=stream)
+    wcap = int(sizing.res.word_bytes) + int(sizing.res.word_bytes) // 4 + 4096
+    slots = 1 << (2 * int(sizing.res.table_slots) - 1).bit_length() if per_doc else 0
+    del sizing
+    o = _opts(count_bytes, per_doc, slots, None, 0, 0, wcap)
     need = ctypes.c_uint64()
     st = lib().wc_autotune_plan(corpus.numel(), n_docs, ctypes.byref(o), ctypes.byref(need))
     if st != WC_OK:
