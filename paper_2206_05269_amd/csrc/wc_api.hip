@@ -17,9 +17,10 @@ thread_local int32_t g_last_hip = 0;
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultLds = 2048;
 constexpr uint32_t kDefaultBlock = 512;
-constexpr uint32_t kSpillLds = 4096;          // pass-1 LDS table entries
 constexpr uint32_t kReduceLds = 7680;         // pass-2 LDS table entries (150 KiB)
 constexpr uint64_t kSpillMinBytes = 64ull << 20;
+constexpr uint32_t kGlobalStage = 8192;       // stage of the two-pass kernels (512 x 16 bytes)
+constexpr uint64_t kMaxWgBytes = 1ull << 31;  // text per pass-1 workgroup (32-bit LDS counts)
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
@@ -115,10 +116,15 @@ struct CountLayout {
   void* cub;
   // two-pass global count
   bool spill = false;
-  uint32_t spill_grid = 0, R = 0;
+  uint32_t spill_grid = 0, R = 0, dict_cap = 0;
+  uint64_t spill_spw = 0;
   uint4* arena = nullptr;
   uint32_t* cursor = nullptr;
   uint16_t* fill = nullptr;
+  Slot* sample_table = nullptr;
+  Header* sample_hdr = nullptr;
+  DictImage* dict = nullptr;
+  uint32_t* dict_part = nullptr;
   uint64_t total;
 };
 
@@ -127,6 +133,14 @@ bool use_spill(uint64_t len, const wc_opts* o) {
   if (o->debug_flags & WC_DEBUG_SPILL) return true;
   if (o->debug_flags & (WC_DEBUG_DIRECT | WC_DEBUG_NO_LDS)) return false;
   return len >= kSpillMinBytes;
+}
+
+// The two-pass kernels scan 8 KiB stages; the stage size tunes only the one-pass kernel.
+void global_stage(uint64_t len, const wc_opts* o, Tune* tu) {
+  if (use_spill(len, o)) {
+    tu->stage = kGlobalStage;
+    tu->block = kGlobalStage / 16;
+  }
 }
 
 int64_t base_offset(const uint8_t* corpus) {
@@ -248,17 +262,33 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
   }
   L->spill = use_spill(len, o) && L->n_stages > 0;
   if (L->spill) {
-    uint32_t grid = tu.grid ? tu.grid : (uint32_t)device_cus();
-    if (grid > L->n_stages) grid = (uint32_t)L->n_stages;
-    L->spill_grid = grid;
-    // room for every byte of text as spilled records, plus one open block per workgroup and
-    // partition; a partition that still runs out counts in the global table instead
-    uint64_t blk_bytes = (uint64_t)kBlockRec * 16;
-    uint64_t need = len + (uint64_t)grid * kSpillParts * blk_bytes;
-    L->R = (uint32_t)((need + (uint64_t)kSpillParts * blk_bytes - 1) / ((uint64_t)kSpillParts * blk_bytes));
-    L->arena = B.take<uint4>((uint64_t)kSpillParts * L->R * blk_bytes);
-    L->cursor = B.take<uint32_t>(kSpillParts * 4);
-    L->fill = B.take<uint16_t>((uint64_t)kSpillParts * L->R * 2);
+    // pass 1: one workgroup per CU (or the tuning's grid), contiguous stage ranges of at most
+    // kMaxWgBytes of text each
+    // sized from the stage count at the worst corpus alignment, so that the plan (which
+    // does not know the pointer) and the call lay out the same workspace; a workgroup whose
+    // range starts past the last stage only closes its blocks
+    const uint64_t ns_max = (len + 15 + tu.stage - 1) / tu.stage;
+    uint64_t grid = tu.grid ? tu.grid : (uint64_t)device_cus();
+    grid = std::min<uint64_t>(grid, ns_max);
+    uint64_t spw = (ns_max + grid - 1) / grid;
+    spw = std::min<uint64_t>(spw, kMaxWgBytes / kGlobalStage);
+    grid = (ns_max + spw - 1) / spw;
+    L->spill_grid = (uint32_t)grid;
+    L->spill_spw = spw;
+    L->dict_cap = std::min<uint32_t>(o->tuning && o->tuning->lds_entries ? tu.lds : kDictMax,
+                                     kDictMax);
+    // room for one record per 16 bytes of text, plus the two blocks each workgroup holds
+    // open per partition; a partition that still runs out counts in the global table
+    const uint64_t blk_bytes = (uint64_t)kBlockRec * 16;
+    const uint64_t need = len + 2 * grid * kParts * blk_bytes;
+    L->R = (uint32_t)((need + kParts * blk_bytes - 1) / (kParts * blk_bytes));
+    L->arena = B.take<uint4>((uint64_t)kParts * L->R * blk_bytes);
+    L->cursor = B.take<uint32_t>(kParts * 4);
+    L->fill = B.take<uint16_t>((uint64_t)kParts * L->R * 2);
+    L->sample_table = B.take<Slot>(kSampleSlots * sizeof(Slot));
+    L->sample_hdr = B.take<Header>(sizeof(Header));
+    L->dict = B.take<DictImage>(sizeof(DictImage));
+    L->dict_part = B.take<uint32_t>(grid * L->dict_cap * 4);
   }
   L->total = B.off;
   return true;
@@ -284,15 +314,12 @@ struct Timer {
   }
 };
 
-size_t spill_count_dyn(uint32_t E) {
-  return (size_t)E * 20 + (size_t)kSpillParts * kStageRec * 16 + 3 * (size_t)kSpillParts * 4;
-}
 
 hipError_t ensure_smem_attr() {
   static hipError_t once = [] {
     hipError_t e = set_count_smem(512, 160 * 1024 - 40 * 1024);
     if (e == hipSuccess) e = set_count_smem(256, 160 * 1024 - 24 * 1024);
-    if (e == hipSuccess) e = set_spill_smem(spill_count_dyn(kSpillLds), (size_t)kReduceLds * 20);
+    if (e == hipSuccess) e = set_global_smem(kDictMax, kReduceLds);
     if (e == hipSuccess) e = set_doc_smem((size_t)kDocLds * 24);
     return e;
   }();
@@ -331,6 +358,7 @@ wc_status wc_count_plan(uint64_t corpus_len, uint64_t n_docs, const wc_opts* opt
   if (!opts_ok(opts) || !out) return WC_EINVAL;
   Tune tu;
   if (!resolve_tuning(opts->tuning, &tu)) return WC_EINVAL;
+  global_stage(corpus_len, opts, &tu);
   if (opts->mode == WC_PER_DOC && n_docs >= 0xffffffffull) return WC_EINVAL;
   if (use_doc_kernel(opts)) {
     if (corpus_len >= (1ull << 32)) return WC_EINVAL;  // packed output cursor: 32-bit fields
@@ -359,6 +387,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
   if (!d_offsets) return WC_EINVAL;
   Tune tu;
   if (!resolve_tuning(opts->tuning, &tu)) return WC_EINVAL;
+  global_stage(corpus_len, opts, &tu);
   const bool per_doc = opts->mode == WC_PER_DOC;
   if (per_doc && n_docs >= 0xffffffffull) return WC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -452,36 +481,40 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
       HIPCHK(launch_count(P, per_doc, grid, tu.block, dyn, s));
       if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
     } else {
-      SpillParams Q;
-      Q.corpus = d_corpus;
-      Q.len = corpus_len;
-      Q.offsets = d_offsets;
-      Q.n_docs = n_docs;
-      Q.table = L.table;
-      Q.mask = L.S - 1;
-      Q.occ_limit = occ_limit;
-      Q.key_mask = key_mask_of(opts);
-      Q.hdr = L.hdr;
-      Q.stage_doc = L.stage_doc;
-      Q.base_off = b0;
-      Q.n_stages = L.n_stages;
-      uint32_t sg = L.spill_grid;
-      Q.stages_per_wg = (L.n_stages + sg - 1) / sg;
-      sg = (uint32_t)((L.n_stages + Q.stages_per_wg - 1) / Q.stages_per_wg);
-      uint32_t E = opts->tuning && opts->tuning->lds_entries ? tu.lds : kSpillLds;
+      GlobalParams G;
+      memset(&G, 0, sizeof(G));
+      G.corpus = d_corpus;
+      G.len = corpus_len;
+      G.offsets = d_offsets;
+      G.n_docs = n_docs;
+      G.table = L.table;
+      G.mask = L.S - 1;
+      G.occ_limit = occ_limit;
+      G.key_mask = key_mask_of(opts);
+      G.hdr = L.hdr;
+      G.stage_doc = L.stage_doc;
+      G.base_off = b0;
+      G.n_stages = L.n_stages;
+      G.stages_per_wg = L.spill_spw;
+      G.map_grid = L.spill_grid;
+      G.dict_cap = L.dict_cap;
+      G.dict = L.dict;
+      G.dict_part = L.dict_part;
+      G.sample_table = L.sample_table;
+      G.sample_hdr = L.sample_hdr;
+      G.R = L.R;
+      G.reduce_entries = kReduceLds;
       uint32_t pct = opts->tuning && opts->tuning->lds_load_pct ? opts->tuning->lds_load_pct : 75;
-      Q.lds_entries = E;
-      Q.hot_cap = std::max<uint32_t>(1, (uint32_t)((uint64_t)E * pct / 100));
-      Q.reduce_entries = kReduceLds;
-      Q.R = L.R;
-      Q.arena = L.arena;
-      Q.cursor = L.cursor;
-      Q.fill = L.fill;
-      HIPCHK(launch_fill_zero(L.cursor, kSpillParts * 4, s));
-      if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
-      HIPCHK(launch_spill_count(Q, sg, spill_count_dyn(E), s));
-      if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
-      HIPCHK(launch_spill_reduce(Q, (size_t)kReduceLds * 20, s));
+      pct = std::min<uint32_t>(std::max<uint32_t>(pct, 10), 90);
+      G.reduce_cap = (uint32_t)((uint64_t)kReduceLds * pct / 100);
+      G.arena = L.arena;
+      G.cursor = L.cursor;
+      G.fill = L.fill;
+      HIPCHK(launch_fill_zero(L.cursor, kParts * 4, s));
+      HIPCHK(launch_fill_zero(L.sample_table, kSampleSlots * sizeof(Slot), s));
+      HIPCHK(launch_fill_zero(L.sample_hdr, sizeof(Header), s));
+      HIPCHK(launch_fill_zero(L.dict, sizeof(DictImage), s));
+      HIPCHK(launch_global(G, tm.on ? tm.a : nullptr, tm.on ? tm.b : nullptr, s));
     }
   }
 

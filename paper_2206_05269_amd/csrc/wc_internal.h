@@ -30,13 +30,34 @@ struct CountParams {
   uint32_t no_lds;
 };
 
-// two-pass global count (wc_spill.hip)
-constexpr uint32_t kSpillParts = 256;  // partitions of the spilled records
-constexpr uint32_t kStageRec = 8;      // records staged per partition in LDS (128 bytes)
-constexpr uint32_t kBlockRec = 256;    // records per arena block (4 KiB)
-constexpr uint32_t kSpillList = 512;   // records a stage can spill before the fallback
+// two-pass global count (wc_global.hip)
+constexpr uint32_t kParts = 256;         // partitions of the spilled records
+constexpr uint32_t kStageSlots = 12;     // records staged per partition in LDS
+constexpr uint32_t kChunkRec = 8;        // records per write to the arena (128 bytes)
+constexpr uint32_t kBlockRec = 256;      // records per arena block (4 KiB)
+constexpr uint32_t kOverflow = 256;      // records of one stage that found their staging full
+constexpr uint32_t kDictMax = 3072;      // hot-word dictionary capacity (words)
+constexpr uint32_t kDictBuckets = 1024;  // dictionary buckets of 4 slots
+constexpr uint32_t kSampleStages = 512;  // 8 KiB stages sampled to choose the dictionary
+constexpr uint32_t kSampleLds = 2048;    // LDS table of one sampled stage
+constexpr uint64_t kSampleSlots = 1ull << 19;  // device table of the sample
+constexpr uint32_t kSdWin = 64;          // stage-to-document entries cached in LDS
+constexpr uint32_t kDictCols = 64;       // dictionary words totalled per pass-2 workgroup
 
-struct SpillParams {
+// Dictionary of hot words, chosen from a sample and read-only while the text is scanned.
+// Each word sits in one of two 4-slot buckets; a slot holds (20-bit tag << 12) | word index.
+struct DictImage {
+  uint32_t n;            // words (key entries) in the dictionary
+  uint32_t nb;           // buckets in use
+  uint32_t n_high;       // selection: words above the count threshold
+  uint32_t n_low;        // selection: words at the threshold competing for the rest
+  uint32_t hist[256];    // sample counts (clamped at 255) -> number of words
+  uint32_t tags[kDictBuckets * 4];
+  uint4 keys[kDictMax];  // packed words (lo, hi)
+  uint32_t cnt[kDictMax];  // their sample counts (clamped at 255), for hottest-first placement
+};
+
+struct GlobalParams {
   const uint8_t* corpus;
   uint64_t len;
   const uint64_t* offsets;
@@ -50,17 +71,26 @@ struct SpillParams {
   int64_t base_off;
   uint64_t n_stages;
   uint64_t stages_per_wg;
-  uint32_t lds_entries;      // pass-1 LDS table entries (<= 4096)
-  uint32_t hot_cap;          // pass-1 live entries before eviction
-  uint32_t reduce_entries;   // pass-2 LDS table entries
+  uint32_t map_grid;         // pass-1 workgroups
+  uint32_t dict_cap;         // dictionary capacity (<= kDictMax)
+  DictImage* dict;
+  uint32_t* dict_part;       // [map_grid][dict_cap] dictionary hits per pass-1 workgroup
+  Slot* sample_table;        // [kSampleSlots]
+  Header* sample_hdr;
   uint32_t R;                // arena blocks per partition
-  uint4* arena;              // [kSpillParts][R][kBlockRec] records
-  uint32_t* cursor;          // [kSpillParts] blocks taken per partition
-  uint16_t* fill;            // [kSpillParts][R] records per block
+  uint32_t reduce_entries;   // pass-2 LDS table entries
+  uint32_t reduce_cap;       // pass-2 live entries before records go to the global table
+  uint32_t pad0;
+  uint4* arena;              // [kParts][R][kBlockRec] records
+  uint32_t* cursor;          // [kParts] blocks taken per partition
+  uint16_t* fill;            // [kParts][R] records per block
 };
-hipError_t set_spill_smem(size_t count_dyn, size_t reduce_dyn);
-hipError_t launch_spill_count(const SpillParams& P, uint32_t grid, size_t dyn, hipStream_t s);
-hipError_t launch_spill_reduce(const SpillParams& P, size_t dyn, hipStream_t s);
+size_t global_map_dyn(uint32_t dict_cap);
+size_t global_reduce_dyn(uint32_t entries);
+hipError_t set_global_smem(uint32_t dict_cap, uint32_t reduce_entries);
+// Sample, dictionary, pass 1 (between events a and b when given) and pass 2. The sample
+// table, its header, the dictionary image and the cursors must be zero.
+hipError_t launch_global(const GlobalParams& P, hipEvent_t a, hipEvent_t b, hipStream_t s);
 
 // per-document count (wc_docs.hip)
 constexpr uint64_t kWin = 64 * 1024;   // default bytes per work item window

@@ -398,8 +398,24 @@ def hash_words(words: Sequence[bytes], device="cuda") -> list:
     return [int(x) & 0xFFFFFFFFFFFFFFFF for x in d_out[:len(words)].cpu().tolist()]
 
 
+def output_sizes(corpus: torch.Tensor, offsets: torch.Tensor, *, per_doc: bool = True,
+                 count_bytes: int = 4, stream=None) -> dict:
+    """Output sizes (word_bytes_cap, table_slots) for fixed-capacity calls (Batch, autotune)
+    on corpora like this one, from one count of it: the output words do not depend on the
+    launch tuning and get a quarter of headroom; the private-table arena does, and gets twice
+    what this count used (rounded up to a power of two)."""
+    t = count(corpus, offsets, count_bytes=count_bytes, per_doc=per_doc, stream=stream)
+    wb = int(t.res.word_bytes)
+    slots = 1 << (2 * int(t.res.table_slots) - 1).bit_length() if per_doc else 0
+    return {"word_bytes_cap": wb + wb // 4 + 4096, "table_slots": slots}
+
+
 class Batch:
-    """Per-document counting of whole corpora with one captured HIP graph (see wc_batch_*)."""
+    """Per-document counting of whole corpora with one captured HIP graph (see wc_batch_*).
+
+    Output capacity is fixed at creation: word_bytes_cap and table_slots (0 = defaults sized
+    for natural text) bound the words and private tables of every run; a run beyond them
+    raises WcError(WC_ENOMEM). output_sizes() derives both from a representative corpus."""
 
     def __init__(self, max_docs: int, max_bytes: int, *, count_bytes: int = 4,
                  tuning: Optional[Tuning] = None, word_bytes_cap: int = 0, table_slots: int = 0,
@@ -568,14 +584,10 @@ def autotune(corpus: torch.Tensor, offsets: torch.Tensor, *, per_doc: bool = Tru
         if key in cache:
             return Tuning(*cache[key]["tuning"])
     n_docs = offsets.numel() - 1
-    # Size the outputs once: the counts (hence the output words) do not depend on the tuning;
-    # the private-table arena does, so it gets twice what a default-tuned count used. Grid
-    # points that still run out of room are skipped by the library.
-    sizing = count(corpus, offsets, count_bytes=count_bytes, per_doc=per_doc, stream=stream)
-    wcap = int(sizing.res.word_bytes) + int(sizing.res.word_bytes) // 4 + 4096
-    slots = 1 << (2 * int(sizing.res.table_slots) - 1).bit_length() if per_doc else 0
-    del sizing
-    o = _opts(count_bytes, per_doc, slots, None, 0, 0, wcap)
+    # grid points that still run out of room are skipped by the library
+    sz = output_sizes(corpus, offsets, per_doc=per_doc, count_bytes=count_bytes, stream=stream)
+    o = _opts(count_bytes, per_doc, sz["table_slots"] if per_doc else 0, None, 0, 0,
+              sz["word_bytes_cap"])
     need = ctypes.c_uint64()
     st = lib().wc_autotune_plan(corpus.numel(), n_docs, ctypes.byref(o), ctypes.byref(need))
     if st != WC_OK:

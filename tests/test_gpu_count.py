@@ -275,7 +275,8 @@ def test_tuning_points_agree(stage, lds, policy, grid, no_lds):
 @pytest.mark.parametrize("lds,grid,pct", [(256, 0, 75), (256, 1, 50), (1024, 3, 90),
                                           (4096, 0, 75), (512, 7, 10)])
 def test_spill_tuning_points(lds, grid, pct):
-    """Small LDS tables force evictions at every stage; tiny grids force long ranges."""
+    """Small dictionaries send most tokens through the partitions; tiny grids give each
+    pass-1 workgroup a long range; low loads send pass-2 overflow to the global table."""
     c = synth.generate("plain-1MB")
     tu = wc.make_tuning(lds_entries=lds, grid_blocks=grid, lds_load_pct=pct)
     check(c.text.numpy(), c.offsets.numpy(), tuning=tu, debug_flags=wc.WC_DEBUG_SPILL)
@@ -319,7 +320,8 @@ def test_per_doc_output_growth():
 
 
 def test_spill_heavy_counts():
-    """Records with counts above one (evictions, final flushes) and counts above 32767."""
+    """Dictionary words with large totals next to a Zipf tail that goes through the
+    partitions; one pass-1 workgroup for the whole text."""
     rng = np.random.default_rng(5)
     words = [b"w%d" % i for i in range(3000)]
     idx = np.minimum(rng.zipf(1.3, size=300_000), 3000) - 1
@@ -327,6 +329,51 @@ def test_spill_heavy_counts():
     tu = wc.make_tuning(lds_entries=512, lds_load_pct=60)
     check(text, tuning=tu, debug_flags=wc.WC_DEBUG_SPILL)
     check(text, tuning=wc.make_tuning(grid_blocks=1), debug_flags=wc.WC_DEBUG_SPILL)
+
+
+def _part_of(word: bytes) -> int:
+    """Partition of a short word in the two-pass kernels (their 32-bit word hash, low 8 bits);
+    used only to build inputs that crowd one partition."""
+    b = word.lower().ljust(16, b"\0")
+    a, b_, c, d = (int.from_bytes(b[i:i + 4], "little") for i in (0, 4, 8, 12))
+    m = 0xffffffff
+    h = ((a * 0x9E3779B1) ^ (b_ * 0x85EBCA77) ^ (c * 0xC2B2AE3D) ^ (d * 0x27D4EB2F)) & m
+    h ^= h >> 15
+    h = (h * 0x2C1B3C6D) & m
+    h ^= h >> 13
+    return h & 255
+
+
+def test_two_pass_crowded_partition():
+    """Thousands of distinct words of one partition in every stage: the LDS staging of that
+    partition fills, the overflow list fills, and the rest goes to the global table."""
+    rng = np.random.default_rng(11)
+    words = set()
+    while len(words) < 6000:
+        w = bytes(rng.choice(list(b"abcdefghijklmnopqrstuvwxyz"), int(rng.integers(3, 9))))
+        if _part_of(w) == 0:
+            words.add(w)
+    words = sorted(words)
+    seq = [words[i] for i in rng.permutation(np.repeat(np.arange(len(words)), 2))]
+    text = b" ".join(seq)
+    for lds in (256, 4096):
+        check(text, tuning=wc.make_tuning(lds_entries=lds), debug_flags=wc.WC_DEBUG_SPILL)
+    check(text, [0, len(text) // 2, len(text)], tuning=wc.make_tuning(grid_blocks=1),
+          debug_flags=wc.WC_DEBUG_SPILL)
+
+
+def test_two_pass_document_edges():
+    """Documents that start on, just before and just after 8 KiB stage edges, and a stretch of
+    5-byte documents (more document starts in a stage than threads in a workgroup)."""
+    text = synth.random_text(200_000, 3, alphabet=b"abcdeXY' .,\n")
+    n = len(text)
+    off = {0, n}
+    for k in range(1, 24):
+        off |= {k * 8192 + d for d in (-17, -16, -15, -1, 0, 1, 15, 16, 17)}
+    off |= set(range(100_000, 120_000, 5))
+    offs = sorted(o for o in off if 0 <= o <= n)
+    check(text, offs, debug_flags=wc.WC_DEBUG_SPILL)
+    check(text, offs, tuning=wc.make_tuning(grid_blocks=3), debug_flags=wc.WC_DEBUG_SPILL)
 
 
 # ------------------------------------------------------------------------------------------
@@ -553,7 +600,8 @@ def test_autotune_choice_is_exact_and_cached(tmp_path):
     assert (tu2.lds_entries, tu2.chunk_bytes, tu2.lds_load_pct) == \
         (tu.lds_entries, tu.chunk_bytes, tu.lds_load_pct)
     check(c.text.numpy(), c.offsets.numpy(), per_doc=True, tuning=tu)
-    b = wc.Batch(max_docs=len(c.offsets), max_bytes=len(c.text), tuning=tu)
+    b = wc.Batch(max_docs=len(c.offsets), max_bytes=len(c.text), tuning=tu,
+                 **wc.output_sizes(t, o))
     got = b.run(t, o)
     assert got.as_dict() == oracle.count(c.text.numpy(), c.offsets.numpy(), per_doc=True).as_dict()
     b.close()
