@@ -27,6 +27,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of pass 1 from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by a device copy of known size), or None once the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "global_map_kernel_stream-8GiB.traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    return int(rec["traffic_bytes"]) if sha == rec["source_sha256"] else None
+
+
 def cpu_baseline(corpus, sample_bytes: int):
     """Time the oracle (single-threaded CPU) on the first sample_bytes of the corpus."""
     import numpy as np
@@ -141,7 +157,7 @@ def main():
         "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "global_map_kernel",
+                     "traffic": measured_traffic(), "kernel": "global_map_kernel",
                      "kernel_ms": round(k_avg, 4), "algorithmic_bytes": alg_bytes},
     }
     if not args.no_cpu:
