@@ -17,9 +17,8 @@ thread_local int32_t g_last_hip = 0;
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultLds = 2048;
 constexpr uint32_t kDefaultBlock = 512;
-constexpr uint32_t kReduceLds = 7680;         // pass-2 LDS table entries (150 KiB)
+constexpr uint32_t kReduceLds = 6912;         // pass-2 LDS table entries (135 KiB)
 constexpr uint64_t kSpillMinBytes = 64ull << 20;
-constexpr uint32_t kGlobalStage = 8192;       // stage of the two-pass kernels (512 x 16 bytes)
 constexpr uint64_t kMaxWgBytes = 1ull << 31;  // text per pass-1 workgroup (32-bit LDS counts)
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -116,7 +115,7 @@ struct CountLayout {
   void* cub;
   // two-pass global count
   bool spill = false;
-  uint32_t spill_grid = 0, R = 0, dict_cap = 0;
+  uint32_t spill_grid = 0, R = 0, static_blocks = 0, dict_cap = 0;
   uint64_t spill_spw = 0;
   uint4* arena = nullptr;
   uint32_t* cursor = nullptr;
@@ -135,7 +134,8 @@ bool use_spill(uint64_t len, const wc_opts* o) {
   return len >= kSpillMinBytes;
 }
 
-// The two-pass kernels scan 8 KiB stages; the stage size tunes only the one-pass kernel.
+// The two-pass kernels scan kGlobalStage-byte stages; the stage size tunes only the one-pass
+// kernel.
 void global_stage(uint64_t len, const wc_opts* o, Tune* tu) {
   if (use_spill(len, o)) {
     tu->stage = kGlobalStage;
@@ -277,11 +277,15 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
     L->spill_spw = spw;
     L->dict_cap = std::min<uint32_t>(o->tuning && o->tuning->lds_entries ? tu.lds : kDictMax,
                                      kDictMax);
-    // room for one record per 16 bytes of text, plus the two blocks each workgroup holds
-    // open per partition; a partition that still runs out counts in the global table
+    // Each workgroup owns J interleaved blocks of every partition: room for one record per
+    // 16 bytes of text spread evenly, plus one block; a quarter more is handed out on demand
+    // to workgroups that need it. A partition that still runs out counts in the global table.
     const uint64_t blk_bytes = (uint64_t)kBlockRec * 16;
-    const uint64_t need = len + 2 * grid * kParts * blk_bytes;
-    L->R = (uint32_t)((need + kParts * blk_bytes - 1) / (kParts * blk_bytes));
+    const uint64_t per = grid * kParts * kBlockRec;  // records per static round of blocks
+    const uint64_t J = (len / 16 + per - 1) / per + 1;
+    const uint64_t S = J * grid;
+    L->static_blocks = (uint32_t)S;
+    L->R = (uint32_t)(S + std::max<uint64_t>(64, S / 4));
     L->arena = B.take<uint4>((uint64_t)kParts * L->R * blk_bytes);
     L->cursor = B.take<uint32_t>(kParts * 4);
     L->fill = B.take<uint16_t>((uint64_t)kParts * L->R * 2);
@@ -503,6 +507,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
       G.sample_table = L.sample_table;
       G.sample_hdr = L.sample_hdr;
       G.R = L.R;
+      G.S = L.static_blocks;
       G.reduce_entries = kReduceLds;
       uint32_t pct = opts->tuning && opts->tuning->lds_load_pct ? opts->tuning->lds_load_pct : 75;
       pct = std::min<uint32_t>(std::max<uint32_t>(pct, 10), 90);
@@ -511,6 +516,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
       G.cursor = L.cursor;
       G.fill = L.fill;
       HIPCHK(launch_fill_zero(L.cursor, kParts * 4, s));
+      HIPCHK(launch_fill_zero(L.fill, (uint64_t)kParts * L.R * 2, s));
       HIPCHK(launch_fill_zero(L.sample_table, kSampleSlots * sizeof(Slot), s));
       HIPCHK(launch_fill_zero(L.sample_hdr, sizeof(Header), s));
       HIPCHK(launch_fill_zero(L.dict, sizeof(DictImage), s));

@@ -263,7 +263,9 @@ WC_DEV bool id_equal(const WordId& id, uint64_t s0, uint64_t s1, uint32_t sdoc1)
 }
 
 // Insert `n` occurrences of a word with key `key` into the table. Returns the slot index,
-// or ~0 when no slot was found after probing every slot (then the full flag is set).
+// or ~0 when no slot was found: after probing every slot (then the full flag is set), or
+// once the full flag is set by any insert (the call then fails as full and its counts are
+// discarded, so probing a crowded table further would only waste time).
 // kPerDoc selects the 32-bit count layout.
 //
 // The probe loop is wave-uniform (it runs while any active lane has work), so a lane that
@@ -325,6 +327,8 @@ WC_DEV uint64_t table_insert(Slot* __restrict__ tab, uint64_t mask, uint64_t key
         if (++probe > mask) {
           or32(&hdr->flags, kFlagTableFull);
           active = false;
+        } else if ((probe & 63) == 0 && (ld_relaxed32(&hdr->flags) & kFlagTableFull)) {
+          active = false;  // the call fails as full anyway: stop probing a crowded table
         }
       }
     }

@@ -37,16 +37,11 @@ WC_DEV uint32_t word_hash32(uint64_t lo, uint64_t hi) {
 
 WC_DEV uint32_t part_of(uint32_t h) { return h & (kParts - 1); }
 
-// dictionary placement: bucket 1 from the high bits of h; tag (low 20 bits) and bucket 2
-// (high bits) from a second mix
-WC_DEV uint32_t dict_h2(uint32_t h) {
-  uint32_t x = h * 0x85EBCA77u;
-  x ^= x >> 16;
-  x *= 0xC2B2AE3Du;
-  x ^= x >> 13;
-  return x;
-}
-WC_DEV uint32_t dict_tag(uint32_t h2) { return (h2 & 0xFFFFFu) | 1u; }
+// The 32-bit word hash h serves three independent uses: partition = bits 0-7, dictionary tag
+// = bits 8-14 (with bit 7 of the tag byte set, so a tag is never 0), dictionary bucket = the
+// high bits (the high half of h * buckets).
+WC_DEV uint32_t dict_tag(uint32_t h) { return ((h >> 8) & 0x7fu) | 0x80u; }
+WC_DEV uint32_t dict_bucket(uint32_t h, uint32_t nb) { return __umulhi(h, nb); }
 
 WC_DEV uint4 key4(uint64_t lo, uint64_t hi) {
   return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
@@ -57,26 +52,21 @@ WC_DEV uint64_t short_key_g(uint64_t lo, uint64_t hi, uint64_t key_mask) {
   return finish_key(fnv_packed(lo, hi, packed_len(lo, hi)), key_mask);
 }
 
-// Index of the word in the dictionary, or -1.
-WC_DEV int dict_find(const uint4* tags4, const uint4* keys, uint32_t nb, uint64_t lo,
-                     uint64_t hi, uint32_t h) {
-  const uint32_t h2 = dict_h2(h);
-  const uint32_t tag = dict_tag(h2);
+// Index of the word in the dictionary, or -1: one 8-byte read of the bucket's tags, a SWAR
+// match of the tag against all 8 (a flagged byte above a true match may be spurious; the key
+// compare settles every candidate), and a key read per candidate.
+WC_DEV int dict_find(const uint64_t* tags8, const uint16_t* idx, const uint4* keys, uint32_t nb,
+                     uint64_t lo, uint64_t hi, uint32_t h) {
+  const uint32_t b = dict_bucket(h, nb);
+  const uint64_t x = tags8[b] ^ (0x0101010101010101ull * dict_tag(h));
+  uint64_t z = (x - 0x0101010101010101ull) & ~x & 0x8080808080808080ull;
   const uint4 want = key4(lo, hi);
-  uint32_t b = __umulhi(h, nb);
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const uint4 t = tags4[b];
-    const uint32_t e[4] = {t.x, t.y, t.z, t.w};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if ((e[j] >> 12) == tag) {
-        const uint32_t idx = e[j] & 0xfffu;
-        const uint4 k = keys[idx];
-        if (k.x == want.x && k.y == want.y && k.z == want.z && k.w == want.w) return (int)idx;
-      }
-    }
-    b = __umulhi(h2, nb);
+  while (z) {
+    const uint32_t j = (uint32_t)(__ffsll((unsigned long long)z) - 1) >> 3;
+    const uint32_t i = idx[b * 8 + j];
+    const uint4 k = keys[i];
+    if (k.x == want.x && k.y == want.y && k.z == want.z && k.w == want.w) return (int)i;
+    z &= z - 1;
   }
   return -1;
 }
@@ -256,34 +246,57 @@ WC_DEV void pack_word(const uint8_t* s_txt, uint32_t s, uint32_t wl, uint64_t* l
   *hi = b;
 }
 
-// Block-wide compaction of the word starts of a stage (one 16-bit mask per thread) into
-// s_starts, in text order. Returns the number of starts. Contains two barriers.
-template <int BLOCK>
-WC_DEV uint32_t compact_starts(uint32_t start16, uint32_t* s_wsum, uint16_t* s_starts) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t cnt = __popc(start16);
-  uint32_t incl = cnt;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += y;
-  }
-  if (lane == 63) s_wsum[wave] = incl;
-  __syncthreads();
-  uint32_t base = 0, total = 0;
-#pragma unroll
-  for (int w = 0; w < BLOCK / 64; ++w) {
-    uint32_t v = s_wsum[w];
-    base += w < wave ? v : 0u;
-    total += v;
-  }
-  uint32_t o = base + incl - cnt;
-  uint32_t m = start16;
+// Inclusive prefix sum over the 64 lanes of a wave: shifts within each 16-lane row, then the
+// row broadcasts of lanes 15 and 31 (lanes whose source is outside the row, and rows the mask
+// leaves out, add 0).
+WC_DEV uint32_t wave_incl_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
+// Positions (tid * 16 + bit) of the starts in mask m whose ranks, counted from `rank`, fall
+// in [w0, w0 + cap), stored at s_starts[rank - w0].
+WC_DEV void write_starts(uint32_t m, uint32_t rank, uint32_t w0, uint32_t cap,
+                         uint16_t* s_starts) {
+  const uint32_t pos0 = threadIdx.x * 16;
   while (m) {
-    int j = __ffs(m) - 1;
-    s_starts[o++] = (uint16_t)(tid * 16 + j);
+    const int j = __ffs(m) - 1;
+    if (rank - w0 < cap) s_starts[rank - w0] = (uint16_t)(pos0 + j);
+    ++rank;
     m &= m - 1;
   }
+}
+
+// Block-wide compaction of the word starts of a stage (one 16-bit mask per thread), in text
+// order: the starts of rank < cap go to s_starts; *rank0 = the rank of this thread's first
+// start, for later windows. Returns the number of starts. Contains two barriers.
+template <int BLOCK>
+WC_DEV uint32_t compact_starts(uint32_t start16, uint32_t* s_wsum, uint16_t* s_starts,
+                               uint32_t cap, uint32_t* rank0) {
+  constexpr int NW = BLOCK / 64;
+  static_assert(NW <= 16, "wave totals are scanned within one 16-lane row");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t cnt = __popc(start16);
+  const uint32_t incl = wave_incl_scan(cnt);
+  if (lane == 63) s_wsum[wave] = incl;
+  __syncthreads();
+  const uint32_t ws = lane < NW ? s_wsum[lane] : 0u;
+  uint32_t wi = ws;
+  wi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wi, 0x111, 0xf, 0xf, false);
+  wi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wi, 0x112, 0xf, 0xf, false);
+  wi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wi, 0x114, 0xf, 0xf, false);
+  wi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wi, 0x118, 0xf, 0xf, false);
+  const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(wi - ws), wave);
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)wi, NW - 1);
+  const uint32_t o = base + incl - cnt;
+  *rank0 = o;
+  write_starts(start16, o, 0, cap, s_starts);
   __syncthreads();
   return total;
 }
@@ -308,7 +321,7 @@ __global__ __launch_bounds__(BLOCK) void sample_kernel(GlobalParams P) {
   if (ld_relaxed32(&P.hdr->flags) & kFlagBadOffsets) return;
   const int64_t R0 = (int64_t)P.offsets[0], R1 = (int64_t)P.offsets[P.n_docs];
   const uint64_t k = (uint64_t)blockIdx.x * P.n_stages / gridDim.x;
-  const int64_t ls = P.base_off + (int64_t)(k * STAGE);
+  const int64_t ls = P.base_off + (int64_t)(k * kGlobalStage);  // first STAGE bytes of it
   uint32_t w16;
   uint4 g = classify16(load_text16(P.corpus, P.len, ls + tid * 16), &w16);
   w16 = cut16(w16, ls + tid * 16, R0, R1);
@@ -331,7 +344,10 @@ __global__ __launch_bounds__(BLOCK) void sample_kernel(GlobalParams P) {
   const uint32_t start16 = w16 & ~((w16 << 1) | prev) & 0xffffu;
   const uint32_t last16 = w16 & ~((w16 >> 1) | (next << 15)) & 0xffffu;
   s_last[tid] = (uint16_t)last16;
-  const uint32_t total = compact_starts<BLOCK>(start16, s_wsum, s_starts);
+  uint32_t rank0;
+  // without document boundaries a start follows a delimiter, so a stage has <= STAGE / 2
+  const uint32_t total =
+      min(compact_starts<BLOCK>(start16, s_wsum, s_starts, STAGE / 2, &rank0), (uint32_t)STAGE / 2);
   const uint32_t cap = kSampleLds - kSampleLds / 4;
   for (uint32_t t = tid; t < total; t += BLOCK) {
     const uint32_t s = s_starts[t];
@@ -421,9 +437,9 @@ __global__ void dict_select_kernel(GlobalParams P) {
   }
 }
 
-// One workgroup: place the selected words into buckets, hottest first (a counting sort on
-// the sample counts), each into the emptier of its two buckets. A word that finds both
-// buckets full is left out, so only the coldest words can be left out.
+// One workgroup: place the selected words into their buckets, hottest first (a counting sort
+// on the sample counts). A word whose bucket is full is left out, so only the coldest words
+// can be left out.
 __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
   __shared__ uint32_t s_fill[kDictBuckets];
   __shared__ uint32_t s_pos[256];
@@ -454,27 +470,22 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
   for (uint32_t i = tid; i < n; i += blockDim.x)
     s_order[atomicAdd(&s_pos[P.dict->cnt[i]], 1u)] = (uint16_t)i;
   __syncthreads();
-  uint32_t nb = (P.dict_cap + 2) / 3;
+  uint32_t nb = (P.dict_cap + 3) / 4;  // half-full buckets
   nb = nb < 16 ? 16 : (nb > kDictBuckets ? kDictBuckets : nb);
+  uint8_t* tag_bytes = (uint8_t*)P.dict->tags;
   for (uint32_t r0 = 0; r0 < n; r0 += blockDim.x) {
     const uint32_t r = r0 + tid;
     if (r < n) {
       const uint32_t i = s_order[r];
       const uint4 k = P.dict->keys[i];
       const uint64_t lo = (uint64_t)k.x | ((uint64_t)k.y << 32), hi = (uint64_t)k.z | ((uint64_t)k.w << 32);
-      const uint32_t h = word_hash32(lo, hi), h2 = dict_h2(h);
-      uint32_t b = __umulhi(h, nb), b2 = __umulhi(h2, nb);
-      if (s_fill[b2] < s_fill[b]) {
-        const uint32_t x = b;
-        b = b2;
-        b2 = x;
+      const uint32_t h = word_hash32(lo, hi);
+      const uint32_t b = dict_bucket(h, nb);
+      const uint32_t slot = atomicAdd(&s_fill[b], 1u);
+      if (slot < 8) {
+        tag_bytes[b * 8 + slot] = (uint8_t)dict_tag(h);
+        P.dict->idx[b * 8 + slot] = (uint16_t)i;
       }
-      uint32_t slot = atomicAdd(&s_fill[b], 1u);
-      if (slot >= 4) {
-        b = b2;
-        slot = atomicAdd(&s_fill[b], 1u);
-      }
-      if (slot < 4) P.dict->tags[b * 4 + slot] = (dict_tag(h2) << 12) | i;
     }
     __syncthreads();  // the next (colder) round sees these placements
   }
@@ -489,15 +500,20 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
 // pass 1
 // ---------------------------------------------------------------------------------------
 size_t global_map_dyn(uint32_t dict_cap) {
-  constexpr int BLOCK = 512;
-  return (size_t)kParts * kStageSlots * 16 + (size_t)(BLOCK + 2) * 16 + (size_t)kDictBuckets * 16 +
-         (size_t)dict_cap * 20 + (size_t)BLOCK * 16;
+  return (size_t)kParts * kStageSlots * 16 + (size_t)(kMapBlock + 2) * 16 +
+         (size_t)kDictBuckets * (8 + 16) + (size_t)dict_cap * 20 + (size_t)kGlobalStage;
 }
 
+// One workgroup of BLOCK threads scans a contiguous range of STAGE-byte stages, 16 bytes per
+// thread per stage. Per stage: classify and mark document starts; word start / last masks and
+// a block-wide compaction of the starts; tokens in rounds of BLOCK, each round followed by the
+// flush of full 128-byte chunks from the partition staging.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   constexpr int STAGE = BLOCK * 16;
   constexpr uint32_t kNone = 0xffffffffu;
+  constexpr uint32_t kStartCap = STAGE / 2;  // word starts held at once (u16 each)
+  static_assert(STAGE == (int)kGlobalStage, "stage size shared with the host layout");
   static_assert(BLOCK >= (int)kParts && BLOCK >= (int)kOverflow && BLOCK >= (int)kSdWin + 3,
                 "one thread per partition, overflow entry and cached stage entry");
   extern __shared__ __align__(16) uint8_t s_dyn[];
@@ -505,6 +521,8 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   __shared__ uint16_t s_last[BLOCK + 1];
   __shared__ uint32_t s_bnd[STAGE / 32 + 2];
   __shared__ uint32_t s_fill[kParts];
+  __shared__ uint32_t s_blk[kParts];
+  __shared__ uint16_t s_bpos[kParts];
   __shared__ uint4 s_ovf[kOverflow];
   __shared__ uint16_t s_ovp[kOverflow];
   __shared__ uint64_t s_sd[kSdWin + 3];
@@ -516,8 +534,9 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   const uint32_t D = P.dict_cap;
   uint4* s_stage = (uint4*)s_dyn;                         // [kParts][kStageSlots]
   uint4* s_txt4 = s_stage + kParts * kStageSlots;         // [BLOCK + 2]
-  uint4* s_tags4 = s_txt4 + (BLOCK + 2);                  // [kDictBuckets]
-  uint4* s_keys = s_tags4 + kDictBuckets;                 // [D]
+  uint64_t* s_tags8 = (uint64_t*)(s_txt4 + (BLOCK + 2));  // [kDictBuckets]
+  uint16_t* s_idx = (uint16_t*)(s_tags8 + kDictBuckets);  // [kDictBuckets * 8]
+  uint4* s_keys = (uint4*)(s_idx + kDictBuckets * 8);     // [D]
   uint32_t* s_cnt = (uint32_t*)(s_keys + D);              // [D]
   uint16_t* s_starts = (uint16_t*)(s_cnt + D);            // [STAGE / 2]
   const uint8_t* s_txt = (const uint8_t*)s_txt4;
@@ -533,7 +552,8 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
 
   // dictionary into LDS
   const uint32_t nd = P.dict->n, nb = P.dict->nb;
-  for (uint32_t i = tid; i < nb; i += BLOCK) s_tags4[i] = ((const uint4*)P.dict->tags)[i];
+  for (uint32_t i = tid; i < nb; i += BLOCK) s_tags8[i] = P.dict->tags[i];
+  for (uint32_t i = tid; i < nb * 8; i += BLOCK) s_idx[i] = P.dict->idx[i];
   for (uint32_t i = tid; i < nd; i += BLOCK) {
     s_keys[i] = P.dict->keys[i];
     s_cnt[i] = 0;
@@ -543,50 +563,88 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   if (tid < 4) s_stat[tid] = 0;
   for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
 
-  // Thread p < kParts writes partition p: current block, records in it, next block.
-  uint32_t blk = kNone, bpos = 0, nxt = kNone;
-  bool nxt_req = false;
-  if (tid < (int)kParts) blk = atomicAdd(&P.cursor[tid], 1u);
-
-  // n (<= kChunkRec) staged records of partition p to the arena (thread p)
-  auto put = [&](uint32_t p, uint32_t n) {
-    const uint4* src = s_stage + p * kStageSlots;
-    if (blk >= P.R) {
-      // the partition's region is exhausted: count these in the global table
-      atomicAdd(&s_stat[1], n);
-      for (uint32_t j = 0; j < n; ++j) {
-        const uint4 r = src[j];
-        const uint64_t lo = (uint64_t)r.x | ((uint64_t)r.y << 32);
-        const uint64_t hi = (uint64_t)r.z | ((uint64_t)r.w << 32);
-        table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
-                            short_id(lo, hi, 0), 1, hdr, P.occ_limit);
+  // Partition staging is a ring of kStageSlots records per partition; s_fill[p] packs the
+  // ring head (high 16 bits) and the number of records held (low 16 bits), so a token reserves
+  // its slot with one LDS atomic and a flush moves no records. s_blk[p] is the partition's
+  // current arena block (kNone once the partition's region is exhausted), s_bpos[p] the
+  // records already in it. This workgroup's j-th own block of a partition is j * G + w; past
+  // its S / G own blocks it takes blocks from [S, R) with an atomic.
+  const uint32_t G = gridDim.x, w = blockIdx.x;
+  for (uint32_t p = tid; p < kParts; p += BLOCK) {
+    s_blk[p] = w < P.S ? w : kNone;
+    s_bpos[p] = 0;
+  }
+  auto ring = [](uint32_t head, uint32_t k) -> uint32_t {
+    const uint32_t x = head + k;
+    return x >= kStageSlots ? x - kStageSlots : x;
+  };
+  auto next_block = [&](uint32_t p, uint32_t b) -> uint32_t {
+    if (b + G < P.S) return b + G;
+    const uint32_t d = P.S + atomicAdd(&P.cursor[p], 1u);
+    return d < P.R ? d : kNone;
+  };
+  auto insert_record = [&](const uint4 r) {
+    const uint64_t lo = (uint64_t)r.x | ((uint64_t)r.y << 32);
+    const uint64_t hi = (uint64_t)r.z | ((uint64_t)r.w << 32);
+    table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
+                        short_id(lo, hi, 0), 1, hdr, P.occ_limit);
+  };
+  // Every partition with a full chunk sends it out: all threads, 8 lanes per partition (one
+  // record each, in one wave), the first of the 8 then advances the ring and the block.
+  auto flush_all = [&]() {
+    for (uint32_t task = tid; task < kParts * kChunkRec; task += BLOCK) {
+      const uint32_t q = task / kChunkRec, r = task % kChunkRec;
+      const uint32_t f = s_fill[q];
+      const uint32_t head = f >> 16;
+      uint32_t n = f & 0xffffu;
+      n = n < kStageSlots ? n : kStageSlots;  // reservations past the end overflowed
+      if (n < kChunkRec) continue;
+      const uint32_t b = s_blk[q], bp = s_bpos[q];
+      const uint4 rec = s_stage[q * kStageSlots + ring(head, r)];
+      if (b != kNone) {
+        P.arena[((uint64_t)q * P.R + b) * kBlockRec + bp + r] = rec;
+      } else {
+        atomicAdd(&s_stat[1], 1u);
+        insert_record(rec);
       }
-      return;
-    }
-    uint4* dst = P.arena + ((uint64_t)p * P.R + blk) * kBlockRec + bpos;
-    for (uint32_t j = 0; j < n; ++j) dst[j] = src[j];
-    bpos += n;
-    if (bpos == kBlockRec) {
-      P.fill[(uint64_t)p * P.R + blk] = (uint16_t)kBlockRec;
-      blk = nxt_req ? nxt : atomicAdd(&P.cursor[p], 1u);
-      nxt_req = false;
-      bpos = 0;
-    } else if (!nxt_req && bpos >= kBlockRec / 2) {
-      nxt = atomicAdd(&P.cursor[p], 1u);  // used half a block from now
-      nxt_req = true;
+      if (r == 0) {  // after the 8 reads above (same wave, program order)
+        s_fill[q] = (ring(head, kChunkRec) << 16) | (n - kChunkRec);
+        if (b != kNone) {
+          uint32_t nbp = bp + kChunkRec;
+          if (nbp == kBlockRec) {
+            P.fill[(uint64_t)q * P.R + b] = (uint16_t)kBlockRec;
+            s_blk[q] = next_block(q, b);
+            nbp = 0;
+          }
+          s_bpos[q] = (uint16_t)nbp;
+        }
+      }
     }
   };
-  // a full chunk of partition p leaves; the rest of its staging moves to the front (thread p)
-  auto flush_part = [&](uint32_t p) {
-    const uint32_t f = s_fill[p];
-    uint32_t n = f < kStageSlots ? f : kStageSlots;  // reservations past the end overflowed
-    if (n >= kChunkRec) {
-      put(p, kChunkRec);
-      uint4* st = s_stage + p * kStageSlots;
-      for (uint32_t j = kChunkRec; j < n; ++j) st[j - kChunkRec] = st[j];
-      n -= kChunkRec;
+  // after a token round (all threads, behind a barrier): full chunks leave, then records that
+  // found their staging full are staged again (flushing between attempts)
+  auto flush_round = [&]() {
+    const uint32_t novf = s_novf < kOverflow ? s_novf : kOverflow;
+    flush_all();
+    if (novf) {
+      if (tid == 0) s_stat[2] += novf;
+      bool pend = (uint32_t)tid < novf;
+      const uint4 rec = pend ? s_ovf[tid] : make_uint4(0, 0, 0, 0);
+      const uint32_t pp = pend ? s_ovp[tid] : 0u;
+      __syncthreads();
+      if (tid == 0) s_novf = 0;
+      while (__syncthreads_or(pend)) {
+        if (pend) {
+          const uint32_t old = atomicAdd(&s_fill[pp], 1u);
+          if ((old & 0xffffu) < kStageSlots) {
+            s_stage[pp * kStageSlots + ring(old >> 16, old & 0xffffu)] = rec;
+            pend = false;
+          }
+        }
+        __syncthreads();
+        flush_all();
+      }
     }
-    s_fill[p] = n;
   };
   auto stage_pos = [&](uint64_t k) -> int64_t { return P.base_off + (int64_t)(k * STAGE); };
   const uint4 blank = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
@@ -604,7 +662,7 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
         (q >= R0 && q < R1 && q >= 0 && q < len && is_word_byte(P.corpus[q])) ? 1u : 0u;
   }
   __syncthreads();
-  // document starts of stages st0 and st0 + 1 (thread i holds the i-th of its stage)
+  // document starts of a stage (thread i holds the i-th)
   auto doc_start = [&](uint64_t k) -> uint64_t {
     if (k >= n_stages) return ~0ull;
     const uint64_t c0 = s_sd[k - sd_base], c1 = s_sd[k + 1 - sd_base];
@@ -612,14 +670,76 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   };
   uint64_t bo1 = doc_start(st0), bo2 = doc_start(st0 + 1), bo0;
 
-  // text: this stage and three ahead (one past the range: the next stage's first bytes close
-  // a word that crosses the range end)
-  uint4 cur = load16(st0), n1 = blank, n2 = blank, n3 = blank;
-  if (st0 + 1 <= st1 && st0 + 1 < n_stages) n1 = load16(st0 + 1);
-  if (st0 + 2 <= st1 && st0 + 2 < n_stages) n2 = load16(st0 + 2);
-  if (st0 + 3 <= st1 && st0 + 3 < n_stages) n3 = load16(st0 + 3);
   uint64_t tokens = 0;
   uint32_t spilled = 0;  // records this thread sent to the partitions
+  // one token: count it in the dictionary, stage it as a record, or (longer than 16 bytes)
+  // count it in the global table
+  auto token = [&](uint32_t t, int64_t ls, uint64_t c1, uint32_t next_run) {
+    const uint32_t s = s_starts[t];
+    uint32_t q = s >> 4;
+    const uint32_t bits = (uint32_t)s_last[q] >> (s & 15);
+    uint32_t e;
+    bool crosses = false;
+    if (bits) {
+      e = s + __ffs(bits) - 1;
+    } else {
+      ++q;
+      while (q < BLOCK && s_last[q] == 0) ++q;
+      if (q < BLOCK) {
+        e = q * 16 + __ffs(s_last[q]) - 1;
+      } else {
+        crosses = true;
+        e = STAGE + next_run - 1;
+      }
+    }
+    const uint32_t wl = e - s + 1;
+    uint64_t lo, hi;
+    if (wl <= 16 && !(crosses && next_run >= 16)) {
+      pack_word(s_txt, s, wl, &lo, &hi);
+    } else {
+      // longer than 16 bytes (or running past the bytes staged): from device memory
+      const uint64_t start = (uint64_t)(ls + s);
+      uint64_t limit = start + wl;
+      if (crosses) {
+        limit = (uint64_t)R1;
+        if (c1 <= P.n_docs && P.offsets[c1] < limit) limit = P.offsets[c1];
+      }
+      uint64_t h64;
+      const uint64_t n = scan_word(P.corpus, start, limit, &lo, &hi, &h64);
+      if (n > 16) {
+        table_insert<false>(P.table, P.mask, finish_key(h64, P.key_mask),
+                            long_id(P.corpus + start, n, 0), 1, hdr, P.occ_limit);
+        return;
+      }
+    }
+    const uint32_t h = word_hash32(lo, hi);
+    const int idx = nd ? dict_find(s_tags8, s_idx, s_keys, nb, lo, hi, h) : -1;
+    if (idx >= 0) {
+      atomicAdd(&s_cnt[idx], 1u);
+      return;
+    }
+    spilled += 1;
+    const uint32_t pp = part_of(h);
+    const uint32_t old = atomicAdd(&s_fill[pp], 1u);
+    if ((old & 0xffffu) < kStageSlots) {
+      s_stage[pp * kStageSlots + ring(old >> 16, old & 0xffffu)] = key4(lo, hi);
+    } else {
+      const uint32_t o = atomicAdd(&s_novf, 1u);
+      if (o < kOverflow) {
+        s_ovf[o] = key4(lo, hi);
+        s_ovp[o] = (uint16_t)pp;
+      } else {
+        atomicAdd(&s_stat[1], 1u);
+        table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
+                            short_id(lo, hi, 0), 1, hdr, P.occ_limit);
+      }
+    }
+  };
+
+  // text: this stage and the next (one past the range: the next stage's first bytes close a
+  // word that crosses the range end)
+  uint4 cur = load16(st0), nx = blank;
+  if (st0 + 1 < n_stages) nx = load16(st0 + 1);
 
   for (uint64_t k = st0; k < st1; ++k) {
     const int64_t ls = stage_pos(k);
@@ -636,8 +756,6 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     bo0 = bo1;
     bo1 = bo2;
     bo2 = doc_start(k + 2);
-    uint4 n4 = blank;
-    if (k + 4 <= st1 && k + 4 < n_stages) n4 = load16(k + 4);
 
     // ---- 1. fold + classify; document starts in [ls, le] ---------------------------------
     uint32_t w16;
@@ -658,7 +776,7 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     if (tid == 0) {
       // the next stage's first 16 bytes: a word running over the stage end finishes there
       uint32_t nw;
-      s_txt4[BLOCK] = classify16(n1, &nw);
+      s_txt4[BLOCK] = classify16(nx, &nw);
       int64_t cut_hi = R1;
       const bool doc_at_le = nb1 > 0 && (int64_t)bo1 == le;
       if (nb1 > 0 && (int64_t)bo1 < cut_hi) cut_hi = (int64_t)bo1;
@@ -670,7 +788,14 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
       s_next_w = nw & 1u;
       s_next_run = (uint32_t)__builtin_ctz(~nw | 0x10000u);  // 16: runs past these bytes
     }
+    // the next stage's text: loaded now, used one stage later
+    cur = nx;
+    nx = blank;
+    if (k + 2 <= st1 && k + 2 < n_stages) nx = load16(k + 2);
     __syncthreads();
+    // the previous stage's last chunks leave only now, after the load above: stores and loads
+    // retire in one order, so stores issued just before a text wait would be waited for too
+    flush_round();
 
     // ---- 2. start / last masks, compaction --------------------------------------------
     const uint32_t prev = tid > 0 ? (s_wm[tid - 1] >> 15) : s_carry[(k & 1) ^ 1];
@@ -687,110 +812,52 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
       s_carry[k & 1] = w16 >> 15;
       s_last[BLOCK] = 0;
     }
-    const uint32_t total = compact_starts<BLOCK>(start16, s_wsum, s_starts);
+    uint32_t rank0;
+    const uint32_t total = compact_starts<BLOCK>(start16, s_wsum, s_starts, kStartCap, &rank0);
     tokens += (tid == 0) ? total : 0u;
     for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
     const uint32_t next_run = s_next_run;
 
-    // ---- 3. tokens ----------------------------------------------------------------------
-    for (uint32_t t = tid; t < total; t += BLOCK) {
-      const uint32_t s = s_starts[t];
-      uint32_t q = s >> 4;
-      const uint32_t bits = (uint32_t)s_last[q] >> (s & 15);
-      uint32_t e;
-      bool crosses = false;
-      if (bits) {
-        e = s + __ffs(bits) - 1;
-      } else {
-        ++q;
-        while (q < BLOCK && s_last[q] == 0) ++q;
-        if (q < BLOCK) {
-          e = q * 16 + __ffs(s_last[q]) - 1;
-        } else {
-          crosses = true;
-          e = STAGE + next_run - 1;
-        }
-      }
-      const uint32_t wl = e - s + 1;
-      uint64_t lo, hi;
-      if (wl <= 16 && !(crosses && next_run >= 16)) {
-        pack_word(s_txt, s, wl, &lo, &hi);
-      } else {
-        // longer than 16 bytes (or running past the bytes staged): from device memory
-        const uint64_t start = (uint64_t)(ls + s);
-        uint64_t limit = start + wl;
-        if (crosses) {
-          limit = (uint64_t)R1;
-          if (c1 <= P.n_docs && P.offsets[c1] < limit) limit = P.offsets[c1];
-        }
-        uint64_t h64;
-        const uint64_t n = scan_word(P.corpus, start, limit, &lo, &hi, &h64);
-        if (n > 16) {
-          table_insert<false>(P.table, P.mask, finish_key(h64, P.key_mask),
-                              long_id(P.corpus + start, n, 0), 1, hdr, P.occ_limit);
-          continue;
-        }
-      }
-      const uint32_t h = word_hash32(lo, hi);
-      const int idx = nd ? dict_find(s_tags4, s_keys, nb, lo, hi, h) : -1;
-      if (idx >= 0) {
-        atomicAdd(&s_cnt[idx], 1u);
-        continue;
-      }
-      spilled += 1;
-      const uint32_t pp = part_of(h);
-      const uint32_t slot = atomicAdd(&s_fill[pp], 1u);
-      if (slot < kStageSlots) {
-        s_stage[pp * kStageSlots + slot] = key4(lo, hi);
-      } else {
-        const uint32_t o = atomicAdd(&s_novf, 1u);
-        if (o < kOverflow) {
-          s_ovf[o] = key4(lo, hi);
-          s_ovp[o] = (uint16_t)pp;
-        } else {
-          atomicAdd(&s_stat[1], 1u);
-          table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
-                              short_id(lo, hi, 0), 1, hdr, P.occ_limit);
-        }
-      }
-    }
-    __syncthreads();
-
-    // ---- 4. full chunks leave; overflowed records are staged again ----------------------
-    const uint32_t novf = s_novf < kOverflow ? s_novf : kOverflow;
-    if (tid < (int)kParts) flush_part(tid);
-    if (novf) {
-      if (tid == 0) s_stat[2] += novf;
-      bool pend = (uint32_t)tid < novf;
-      uint4 rec = pend ? s_ovf[tid] : make_uint4(0, 0, 0, 0);
-      uint32_t pp = pend ? s_ovp[tid] : 0u;
-      __syncthreads();
-      if (tid == 0) s_novf = 0;
-      while (__syncthreads_or(pend)) {
-        if (pend) {
-          const uint32_t slot = atomicAdd(&s_fill[pp], 1u);
-          if (slot < kStageSlots) {
-            s_stage[pp * kStageSlots + slot] = rec;
-            pend = false;
-          }
-        }
+    // ---- 3. tokens in rounds of BLOCK; staged chunks leave after each round. Document
+    // boundaries can make every byte a start: starts beyond kStartCap take further windows.
+    for (uint32_t w0 = 0; w0 < total; w0 += kStartCap) {
+      if (w0) {
         __syncthreads();
-        if (tid < (int)kParts) flush_part(tid);
+        write_starts(start16, rank0, w0, kStartCap, s_starts);
+        __syncthreads();
+      }
+      const uint32_t wend = min(total, w0 + kStartCap);
+      for (uint32_t t0 = w0; t0 < wend; t0 += BLOCK) {
+        const uint32_t t = t0 + tid;
+        if (t < wend) token(t - w0, ls, c1, next_run);
+        __syncthreads();
+        if (t0 + BLOCK < wend || w0 + kStartCap < total) {  // the last round's flush waits
+          flush_round();
+          __syncthreads();
+        }
       }
     }
-    cur = n1;
-    n1 = n2;
-    n2 = n3;
-    n3 = n4;
   }
 
   // ---- end of range: staged records leave, blocks close; dictionary hits go out ---------
   __syncthreads();
+  flush_round();
+  __syncthreads();
   if (tid < (int)kParts) {
-    const uint32_t n = s_fill[tid];
-    if (n) put(tid, n);
-    if (blk < P.R) P.fill[(uint64_t)tid * P.R + blk] = (uint16_t)bpos;
-    if (nxt_req && nxt < P.R) P.fill[(uint64_t)tid * P.R + nxt] = 0;
+    // the last (partial) chunk; s_bpos is a multiple of kChunkRec and n < kChunkRec: it fits
+    const uint32_t f = s_fill[tid], head = f >> 16, n = f & 0xffffu;
+    const uint32_t b = s_blk[tid];
+    uint32_t bp = s_bpos[tid];
+    const uint4* src = s_stage + tid * kStageSlots;
+    for (uint32_t j = 0; j < n; ++j) {
+      if (b != kNone) {
+        P.arena[((uint64_t)tid * P.R + b) * kBlockRec + bp + j] = src[ring(head, j)];
+      } else {
+        atomicAdd(&s_stat[1], 1u);
+        insert_record(src[ring(head, j)]);
+      }
+    }
+    if (b != kNone) P.fill[(uint64_t)tid * P.R + b] = (uint16_t)(bp + n);
   }
   for (uint32_t i = tid; i < nd; i += BLOCK) P.dict_part[(uint64_t)blockIdx.x * D + i] = s_cnt[i];
   if (spilled) atomicAdd(&s_stat[0], spilled);
@@ -811,8 +878,9 @@ size_t global_reduce_dyn(uint32_t entries) { return (size_t)entries * 20; }
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   extern __shared__ __align__(16) uint8_t s_dyn[];
-  __shared__ uint32_t s_live, s_miss;
+  __shared__ uint32_t s_live, s_miss, s_nlist;
   __shared__ unsigned long long s_dsum[kDictCols];
+  __shared__ uint16_t s_list[kWinBlocks], s_lfill[kWinBlocks];
   const uint32_t p = blockIdx.x;
   const int tid = threadIdx.x;
   Header* hdr = P.hdr;
@@ -847,47 +915,64 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
     if (v) atomicAdd(&s_dsum[c], (unsigned long long)v);
   }
 
-  // records of partition p
-  const uint32_t nblk = min(P.cursor[p], P.R);
+  // records of partition p: its own blocks of every pass-1 workgroup, then the blocks handed
+  // out past S; the non-empty ones are listed kWinBlocks at a time and read whole
+  const uint32_t nblk = P.S + min(P.cursor[p], P.R - P.S);
   const uint4* region = P.arena + (uint64_t)p * P.R * kBlockRec;
   const uint16_t* fills = P.fill + (uint64_t)p * P.R;
   constexpr uint32_t kPerIter = BLOCK / kBlockRec;  // blocks per iteration
   static_assert(BLOCK % kBlockRec == 0, "whole blocks per iteration");
   const uint32_t cap = P.reduce_cap;
   const uint32_t r_in = tid % kBlockRec, b_in = tid / kBlockRec;
-  auto fetch = [&](uint32_t b0, uint32_t* n) -> uint4 {
-    const uint32_t b = b0 + b_in;
-    if (b >= nblk) {
-      *n = 0;
-      return make_uint4(0, 0, 0, 0);
+  auto add_record = [&](const uint4 v) {
+    const uint64_t lo = (uint64_t)v.x | ((uint64_t)v.y << 32);
+    const uint64_t hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
+    const bool ok = lds_add(T, lo, hi, word_hash32(lo, hi) * 0x9E3779B1u, 1, s_live < cap, &s_live);
+    if (!ok) {
+      atomicAdd(&s_miss, 1u);
+      table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
+                          short_id(lo, hi, 0), 1, hdr, P.occ_limit);
     }
-    *n = fills[b];  // issued with the record load; compared once both arrive
-    return region[(uint64_t)b * kBlockRec + r_in];
   };
-  uint32_t f0, f1, f2;
-  uint4 v0 = fetch(0, &f0);
-  uint4 v1 = fetch(kPerIter, &f1);
-  uint4 v2 = fetch(2 * kPerIter, &f2);
-  for (uint32_t b0 = 0; b0 < nblk; b0 += kPerIter) {
-    uint32_t f3;
-    const uint4 v3 = fetch(b0 + 3 * kPerIter, &f3);
-    if (r_in < f0) {
-      const uint64_t lo = (uint64_t)v0.x | ((uint64_t)v0.y << 32);
-      const uint64_t hi = (uint64_t)v0.z | ((uint64_t)v0.w << 32);
-      const bool ok = lds_add(T, lo, hi, word_hash32(lo, hi) * 0x9E3779B1u, 1,
-                              s_live < cap, &s_live);
-      if (!ok) {
-        atomicAdd(&s_miss, 1u);
-        table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
-                            short_id(lo, hi, 0), 1, hdr, P.occ_limit);
+  for (uint32_t w0 = 0; w0 < nblk; w0 += kWinBlocks) {
+    const uint32_t wn = min(kWinBlocks, nblk - w0);
+    if (tid == 0) s_nlist = 0;
+    __syncthreads();
+    for (uint32_t k = tid; k < wn; k += BLOCK) {
+      const uint32_t f = fills[w0 + k];
+      if (f) {
+        const uint32_t i = atomicAdd(&s_nlist, 1u);
+        s_list[i] = (uint16_t)k;
+        s_lfill[i] = (uint16_t)f;
       }
     }
-    v0 = v1;
-    f0 = f1;
-    v1 = v2;
-    f1 = f2;
-    v2 = v3;
-    f2 = f3;
+    __syncthreads();
+    const uint32_t nl = s_nlist;
+    if (nl == 0) continue;
+    // Records arrive kDepth iterations ahead in a register ring that is never rotated (a move
+    // of a register with a load in flight would wait for it): the loop is unrolled by kDepth.
+    // Loads never branch: past the list's end they read its first block and count nothing.
+    constexpr int kDepth = 4;
+    uint4 v[kDepth];
+    uint32_t f[kDepth];
+#pragma unroll
+    for (int jj = 0; jj < kDepth; ++jj) {
+      const uint32_t e = jj * kPerIter + b_in;
+      const uint32_t ee = e < nl ? e : 0u;
+      f[jj] = e < nl ? s_lfill[ee] : 0u;
+      v[jj] = region[(uint64_t)(w0 + s_list[ee]) * kBlockRec + r_in];
+    }
+    for (uint32_t e0 = 0; e0 < nl; e0 += kDepth * kPerIter) {
+#pragma unroll
+      for (int jj = 0; jj < kDepth; ++jj) {
+        if (r_in < f[jj]) add_record(v[jj]);
+        const uint32_t e = e0 + (jj + kDepth) * kPerIter + b_in;
+        const uint32_t ee = e < nl ? e : 0u;
+        f[jj] = e < nl ? s_lfill[ee] : 0u;
+        v[jj] = region[(uint64_t)(w0 + s_list[ee]) * kBlockRec + r_in];
+      }
+    }
+    __syncthreads();  // the list is rebuilt for the next window
   }
   __syncthreads();
   for (uint32_t i = tid; i < E; i += BLOCK) {
@@ -912,7 +997,7 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
 }
 
 hipError_t set_global_smem(uint32_t dict_cap, uint32_t reduce_entries) {
-  hipError_t e = hipFuncSetAttribute((const void*)global_map_kernel<512>,
+  hipError_t e = hipFuncSetAttribute((const void*)global_map_kernel<kMapBlock>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)global_map_dyn(dict_cap));
   if (e == hipSuccess)
@@ -932,7 +1017,7 @@ hipError_t launch_global(const GlobalParams& P, hipEvent_t a, hipEvent_t b, hipS
     hipError_t e = hipEventRecord(a, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(global_map_kernel<512>, dim3(P.map_grid), dim3(512),
+  hipLaunchKernelGGL(global_map_kernel<kMapBlock>, dim3(P.map_grid), dim3(kMapBlock),
                      global_map_dyn(P.dict_cap), s, P);
   if (b) {
     hipError_t e = hipEventRecord(b, s);

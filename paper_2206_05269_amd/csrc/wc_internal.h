@@ -36,23 +36,28 @@ constexpr uint32_t kStageSlots = 12;     // records staged per partition in LDS
 constexpr uint32_t kChunkRec = 8;        // records per write to the arena (128 bytes)
 constexpr uint32_t kBlockRec = 256;      // records per arena block (4 KiB)
 constexpr uint32_t kOverflow = 256;      // records of one stage that found their staging full
-constexpr uint32_t kDictMax = 3072;      // hot-word dictionary capacity (words)
-constexpr uint32_t kDictBuckets = 1024;  // dictionary buckets of 4 slots
-constexpr uint32_t kSampleStages = 512;  // 8 KiB stages sampled to choose the dictionary
+constexpr uint32_t kDictMax = 2560;      // hot-word dictionary capacity (words)
+constexpr uint32_t kMapBlock = 1024;     // pass-1 workgroup
+constexpr uint32_t kGlobalStage = kMapBlock * 16;  // bytes scanned per pass-1 stage
+constexpr uint32_t kDictBuckets = 640;   // dictionary buckets of 8 slots
+constexpr uint32_t kSampleStages = 512;  // pass-1 stages sampled (first 8 KiB of each)
 constexpr uint32_t kSampleLds = 2048;    // LDS table of one sampled stage
 constexpr uint64_t kSampleSlots = 1ull << 19;  // device table of the sample
 constexpr uint32_t kSdWin = 64;          // stage-to-document entries cached in LDS
 constexpr uint32_t kDictCols = 64;       // dictionary words totalled per pass-2 workgroup
+constexpr uint32_t kWinBlocks = 4096;    // pass 2 lists the non-empty blocks this many at a time
 
 // Dictionary of hot words, chosen from a sample and read-only while the text is scanned.
-// Each word sits in one of two 4-slot buckets; a slot holds (20-bit tag << 12) | word index.
+// A word sits in one 8-slot bucket; a bucket is 8 one-byte tags (0 = empty) in one 64-bit
+// word, and each slot has the 16-bit index of its key.
 struct DictImage {
   uint32_t n;            // words (key entries) in the dictionary
   uint32_t nb;           // buckets in use
   uint32_t n_high;       // selection: words above the count threshold
   uint32_t n_low;        // selection: words at the threshold competing for the rest
   uint32_t hist[256];    // sample counts (clamped at 255) -> number of words
-  uint32_t tags[kDictBuckets * 4];
+  uint64_t tags[kDictBuckets];         // 8 tags per bucket
+  uint16_t idx[kDictBuckets * 8];      // key index of each slot
   uint4 keys[kDictMax];  // packed words (lo, hi)
   uint32_t cnt[kDictMax];  // their sample counts (clamped at 255), for hottest-first placement
 };
@@ -80,16 +85,17 @@ struct GlobalParams {
   uint32_t R;                // arena blocks per partition
   uint32_t reduce_entries;   // pass-2 LDS table entries
   uint32_t reduce_cap;       // pass-2 live entries before records go to the global table
-  uint32_t pad0;
+  uint32_t S;                // static blocks per partition: block j * map_grid + w is the
+                             // j-th of pass-1 workgroup w; blocks [S, R) are handed out
   uint4* arena;              // [kParts][R][kBlockRec] records
-  uint32_t* cursor;          // [kParts] blocks taken per partition
-  uint16_t* fill;            // [kParts][R] records per block
+  uint32_t* cursor;          // [kParts] blocks handed out past S per partition
+  uint16_t* fill;            // [kParts][R] records per block (zero before pass 1)
 };
 size_t global_map_dyn(uint32_t dict_cap);
 size_t global_reduce_dyn(uint32_t entries);
 hipError_t set_global_smem(uint32_t dict_cap, uint32_t reduce_entries);
 // Sample, dictionary, pass 1 (between events a and b when given) and pass 2. The sample
-// table, its header, the dictionary image and the cursors must be zero.
+// table, its header, the dictionary image, the cursors and the block fills must be zero.
 hipError_t launch_global(const GlobalParams& P, hipEvent_t a, hipEvent_t b, hipStream_t s);
 
 // per-document count (wc_docs.hip)

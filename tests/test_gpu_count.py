@@ -376,6 +376,16 @@ def test_two_pass_document_edges():
     check(text, offs, tuning=wc.make_tuning(grid_blocks=3), debug_flags=wc.WC_DEBUG_SPILL)
 
 
+def test_two_pass_one_byte_documents():
+    """Every byte its own document over several stages: each byte of a word run starts a word,
+    so a stage holds more starts than half its bytes."""
+    text = b"ab" * 30_000 + b" x" * 5_000 + synth.random_text(50_000, 4)
+    n = len(text)
+    offs = list(range(0, 60_001)) + [70_000, n]
+    check(text, offs, debug_flags=wc.WC_DEBUG_SPILL)
+    check(text, offs, tuning=wc.make_tuning(lds_entries=256), debug_flags=wc.WC_DEBUG_SPILL)
+
+
 # ------------------------------------------------------------------------------------------
 # synthetic workloads
 # ------------------------------------------------------------------------------------------
