@@ -17,7 +17,7 @@ thread_local int32_t g_last_hip = 0;
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultLds = 2048;
 constexpr uint32_t kDefaultBlock = 512;
-constexpr uint32_t kReduceLds = 6912;         // pass-2 LDS table entries (135 KiB)
+constexpr uint32_t kReduceLds = 5632;         // pass-2 LDS entries (110 KiB + 32 KiB of slots)
 constexpr uint64_t kSpillMinBytes = 64ull << 20;
 constexpr uint64_t kMaxWgBytes = 1ull << 31;  // text per pass-1 workgroup (32-bit LDS counts)
 
@@ -509,8 +509,8 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
       G.R = L.R;
       G.S = L.static_blocks;
       G.reduce_entries = kReduceLds;
-      uint32_t pct = opts->tuning && opts->tuning->lds_load_pct ? opts->tuning->lds_load_pct : 75;
-      pct = std::min<uint32_t>(std::max<uint32_t>(pct, 10), 90);
+      uint32_t pct = opts->tuning && opts->tuning->lds_load_pct ? opts->tuning->lds_load_pct : 100;
+      pct = std::min<uint32_t>(std::max<uint32_t>(pct, 10), 100);
       G.reduce_cap = (uint32_t)((uint64_t)kReduceLds * pct / 100);
       G.arena = L.arena;
       G.cursor = L.cursor;

@@ -871,14 +871,95 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
 }
 
 // ---------------------------------------------------------------------------------------
+// pass-2 LDS table: kRedSlots slots of (19-bit tag << 13 | entry) probed in groups of 4 (one
+// 16-byte read), and dense entries (key, count). A new word takes an entry, writes its key,
+// then claims an empty slot with a CAS; a reader that meets a claimed slot whose key is not
+// visible yet looks again next iteration. Two waves racing on the same new word may give it
+// two entries; both are added to the global table, which sums them.
+// ---------------------------------------------------------------------------------------
+struct RedTable {
+  uint32_t* slot;  // [kRedSlots], 0 = empty
+  uint4* key;      // [cap]
+  uint32_t* cnt;   // [cap]
+  uint32_t* n;     // entries handed out
+  uint32_t cap;
+};
+
+// Add one occurrence. Returns false when the word has no entry and none can be made (entries
+// exhausted or 16 groups probed): the caller counts it in the global table.
+WC_DEV bool red_add(const RedTable& T, uint64_t lo, uint64_t hi, uint32_t h) {
+  constexpr uint32_t kGroups = kRedSlots / 4;
+  constexpr uint32_t kNoEntry = 0xffffffffu;
+  const uint32_t tag = (h & 0x7ffffu) | 1u;
+  uint32_t g = h >> (32 - 11);  // 11 bits: kGroups groups
+  static_assert(kGroups == 2048, "group index takes the hash's top 11 bits");
+  const uint4 want = key4(lo, hi);
+  uint32_t mine = kNoEntry, probe = 0;
+  bool active = true, ok = false;
+  while (__any(active)) {
+    if (active) {
+      const uint4 s4 = ((const uint4*)T.slot)[g];
+      const uint32_t e[4] = {s4.x, s4.y, s4.z, s4.w};
+      bool found = false, wait = false;
+      int free_j = -1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (found) continue;
+        if ((e[j] >> 13) == tag) {
+          const uint32_t idx = e[j] & 0x1fffu;
+          const uint4 k = T.key[idx];
+          if (k.x == want.x && k.y == want.y && k.z == want.z && k.w == want.w) {
+            atomicAdd(&T.cnt[idx], 1u);
+            found = true;
+          } else if ((k.x | k.y) == 0) {
+            wait = true;  // claimed, key not visible yet
+          }
+        } else if (e[j] == 0 && free_j < 0) {
+          free_j = j;
+        }
+      }
+      if (found) {
+        ok = true;
+        active = false;
+      } else if (wait) {
+        // look at this group again
+      } else if (free_j >= 0) {
+        if (mine == kNoEntry) {
+          const uint32_t m = atomicAdd(T.n, 1u);
+          if (m < T.cap) {
+            mine = m;
+            T.key[m] = want;
+          } else {
+            active = false;  // entries exhausted
+          }
+        }
+        if (active) {
+          const uint32_t prev = atomicCAS(&T.slot[g * 4 + free_j], 0u, (tag << 13) | mine);
+          if (prev == 0) {
+            atomicAdd(&T.cnt[mine], 1u);
+            ok = true;
+            active = false;
+          }  // else the slot was taken: look at this group again
+        }
+      } else {
+        g = (g + 1) & (kGroups - 1);
+        if (++probe >= 16) active = false;
+      }
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------------------
 // pass 2: one workgroup per partition
 // ---------------------------------------------------------------------------------------
-size_t global_reduce_dyn(uint32_t entries) { return (size_t)entries * 20; }
+size_t global_reduce_dyn(uint32_t entries) { return (size_t)kRedSlots * 4 + (size_t)entries * 20; }
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   extern __shared__ __align__(16) uint8_t s_dyn[];
-  __shared__ uint32_t s_live, s_miss, s_nlist;
+  __shared__ uint32_t s_nent, s_miss, s_nlist;
   __shared__ unsigned long long s_dsum[kDictCols];
   __shared__ uint16_t s_list[kWinBlocks], s_lfill[kWinBlocks];
   const uint32_t p = blockIdx.x;
@@ -886,19 +967,20 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   Header* hdr = P.hdr;
   if (ld_relaxed32(&hdr->flags) & kFlagBadOffsets) return;
   const uint32_t E = P.reduce_entries;
-  LdsWords T;
-  T.lo = (uint64_t*)s_dyn;
-  T.hi = T.lo + E;
-  T.cnt = (uint32_t*)(T.hi + E);
-  T.size = E;
+  RedTable T;
+  T.slot = (uint32_t*)s_dyn;
+  T.key = (uint4*)(T.slot + kRedSlots);
+  T.cnt = (uint32_t*)(T.key + E);
+  T.n = &s_nent;
+  T.cap = P.reduce_cap < E ? P.reduce_cap : E;
+  for (uint32_t i = tid; i < kRedSlots; i += BLOCK) T.slot[i] = 0;
   for (uint32_t i = tid; i < E; i += BLOCK) {
-    T.lo[i] = 0;
-    T.hi[i] = 0;
+    T.key[i] = make_uint4(0, 0, 0, 0);
     T.cnt[i] = 0;
   }
   for (uint32_t i = tid; i < kDictCols; i += BLOCK) s_dsum[i] = 0;
   if (tid == 0) {
-    s_live = 0;
+    s_nent = 0;
     s_miss = 0;
   }
   __syncthreads();
@@ -922,12 +1004,12 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   const uint16_t* fills = P.fill + (uint64_t)p * P.R;
   constexpr uint32_t kPerIter = BLOCK / kBlockRec;  // blocks per iteration
   static_assert(BLOCK % kBlockRec == 0, "whole blocks per iteration");
-  const uint32_t cap = P.reduce_cap;
   const uint32_t r_in = tid % kBlockRec, b_in = tid / kBlockRec;
   auto add_record = [&](const uint4 v) {
     const uint64_t lo = (uint64_t)v.x | ((uint64_t)v.y << 32);
     const uint64_t hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
-    const bool ok = lds_add(T, lo, hi, word_hash32(lo, hi) * 0x9E3779B1u, 1, s_live < cap, &s_live);
+    // every record of this partition has the same low 8 hash bits: mix before splitting
+    const bool ok = red_add(T, lo, hi, word_hash32(lo, hi) * 0x9E3779B1u);
     if (!ok) {
       atomicAdd(&s_miss, 1u);
       table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
@@ -975,10 +1057,13 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
     __syncthreads();  // the list is rebuilt for the next window
   }
   __syncthreads();
-  for (uint32_t i = tid; i < E; i += BLOCK) {
+  const uint32_t ne = min(s_nent, T.cap);
+  for (uint32_t i = tid; i < ne; i += BLOCK) {
     const uint32_t c = T.cnt[i];
     if (c) {
-      const uint64_t lo = T.lo[i], hi = T.hi[i] & ~kTop;
+      const uint4 k = T.key[i];
+      const uint64_t lo = (uint64_t)k.x | ((uint64_t)k.y << 32);
+      const uint64_t hi = (uint64_t)k.z | ((uint64_t)k.w << 32);
       table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
                           short_id(lo, hi, 0), c, hdr, P.occ_limit);
     }

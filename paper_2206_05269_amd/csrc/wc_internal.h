@@ -45,7 +45,8 @@ constexpr uint32_t kSampleLds = 2048;    // LDS table of one sampled stage
 constexpr uint64_t kSampleSlots = 1ull << 19;  // device table of the sample
 constexpr uint32_t kSdWin = 64;          // stage-to-document entries cached in LDS
 constexpr uint32_t kDictCols = 64;       // dictionary words totalled per pass-2 workgroup
-constexpr uint32_t kWinBlocks = 4096;    // pass 2 lists the non-empty blocks this many at a time
+constexpr uint32_t kWinBlocks = 2048;    // pass 2 lists the non-empty blocks this many at a time
+constexpr uint32_t kRedSlots = 8192;     // pass-2 LDS slots (13-bit entry indices)
 
 // Dictionary of hot words, chosen from a sample and read-only while the text is scanned.
 // A word sits in one 8-slot bucket; a bucket is 8 one-byte tags (0 = empty) in one 64-bit
@@ -83,8 +84,8 @@ struct GlobalParams {
   Slot* sample_table;        // [kSampleSlots]
   Header* sample_hdr;
   uint32_t R;                // arena blocks per partition
-  uint32_t reduce_entries;   // pass-2 LDS table entries
-  uint32_t reduce_cap;       // pass-2 live entries before records go to the global table
+  uint32_t reduce_entries;   // pass-2 LDS entries (distinct words of a partition, <= kRedSlots)
+  uint32_t reduce_cap;       // entries used before further new words go to the global table
   uint32_t S;                // static blocks per partition: block j * map_grid + w is the
                              // j-th of pass-1 workgroup w; blocks [S, R) are handed out
   uint4* arena;              // [kParts][R][kBlockRec] records
