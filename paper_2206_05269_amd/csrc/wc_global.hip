@@ -523,11 +523,13 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   __shared__ uint32_t s_fill[kParts];
   __shared__ uint32_t s_blk[kParts];
   __shared__ uint16_t s_bpos[kParts];
-  __shared__ uint4 s_ovf[kOverflow];
-  __shared__ uint16_t s_ovp[kOverflow];
+  __shared__ uint4 s_ovf[2][kOverflow];    // by token-round parity
+  __shared__ uint16_t s_ovp[2][kOverflow];
   __shared__ uint64_t s_sd[kSdWin + 3];
   __shared__ uint32_t s_wsum[BLOCK / 64];
-  __shared__ uint32_t s_novf, s_next_w, s_next_run;
+  __shared__ uint32_t s_novf[2], s_next_w, s_next_run;
+  __shared__ uint16_t s_full[2][kParts];    // partitions holding a full chunk, by round parity
+  __shared__ uint32_t s_nfull[2];
   __shared__ uint32_t s_carry[2];
   __shared__ uint32_t s_stat[4];
 
@@ -559,7 +561,10 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     s_cnt[i] = 0;
   }
   for (uint32_t p = tid; p < kParts; p += BLOCK) s_fill[p] = 0;
-  if (tid == 0) s_novf = 0;
+  if (tid < 2) {
+    s_novf[tid] = 0;
+    s_nfull[tid] = 0;
+  }
   if (tid < 4) s_stat[tid] = 0;
   for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
 
@@ -589,16 +594,27 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
                         short_id(lo, hi, 0), 1, hdr, P.occ_limit);
   };
-  // Every partition with a full chunk sends it out: all threads, 8 lanes per partition (one
-  // record each, in one wave), the first of the 8 then advances the ring and the block.
-  auto flush_all = [&]() {
-    for (uint32_t task = tid; task < kParts * kChunkRec; task += BLOCK) {
-      const uint32_t q = task / kChunkRec, r = task % kChunkRec;
+  // Every partition listed in s_full[L] holds a full chunk and sends it out: 8 lanes per
+  // partition (one record each, in one wave); the first of the 8 then advances the ring and
+  // the block, and stages the partition's records from overflow list L (a partition overflows
+  // only with a full ring, so it is listed now and has room). A partition still holding a
+  // full chunk is listed for the next round. Lists L ^ 1 were read by the previous flush and
+  // are cleared for the next round.
+  auto flush_all = [&](uint32_t L, bool with_ovf) {
+    const uint32_t novf = with_ovf ? min(s_novf[L], kOverflow) : 0u;
+    const uint32_t nfull = s_nfull[L];
+    if (tid == 0) {
+      s_novf[L ^ 1] = 0;
+      s_stat[2] += novf;
+    }
+    // s_full[L ^ 1] collects partitions for the next round; it was emptied before this
+    // round's tokens ran
+    for (uint32_t task = tid; task < nfull * kChunkRec; task += BLOCK) {
+      const uint32_t q = s_full[L][task / kChunkRec], r = task % kChunkRec;
       const uint32_t f = s_fill[q];
       const uint32_t head = f >> 16;
       uint32_t n = f & 0xffffu;
       n = n < kStageSlots ? n : kStageSlots;  // reservations past the end overflowed
-      if (n < kChunkRec) continue;
       const uint32_t b = s_blk[q], bp = s_bpos[q];
       const uint4 rec = s_stage[q * kStageSlots + ring(head, r)];
       if (b != kNone) {
@@ -608,7 +624,20 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
         insert_record(rec);
       }
       if (r == 0) {  // after the 8 reads above (same wave, program order)
-        s_fill[q] = (ring(head, kChunkRec) << 16) | (n - kChunkRec);
+        const uint32_t nh = ring(head, kChunkRec);
+        uint32_t nc = n - kChunkRec;
+        for (uint32_t i = 0; i < novf; ++i) {
+          if (s_ovp[L][i] != q) continue;
+          if (nc < kStageSlots) {
+            s_stage[q * kStageSlots + ring(nh, nc)] = s_ovf[L][i];
+            ++nc;
+          } else {
+            atomicAdd(&s_stat[1], 1u);
+            insert_record(s_ovf[L][i]);
+          }
+        }
+        s_fill[q] = (nh << 16) | nc;
+        if (nc >= kChunkRec) s_full[L ^ 1][atomicAdd(&s_nfull[L ^ 1], 1u)] = (uint16_t)q;
         if (b != kNone) {
           uint32_t nbp = bp + kChunkRec;
           if (nbp == kBlockRec) {
@@ -621,29 +650,12 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
       }
     }
   };
-  // after a token round (all threads, behind a barrier): full chunks leave, then records that
-  // found their staging full are staged again (flushing between attempts)
+  uint32_t rounds = 0, flushed = 0;  // token rounds done / flushed (uniform)
+  // after a token round (all threads, behind a barrier)
   auto flush_round = [&]() {
-    const uint32_t novf = s_novf < kOverflow ? s_novf : kOverflow;
-    flush_all();
-    if (novf) {
-      if (tid == 0) s_stat[2] += novf;
-      bool pend = (uint32_t)tid < novf;
-      const uint4 rec = pend ? s_ovf[tid] : make_uint4(0, 0, 0, 0);
-      const uint32_t pp = pend ? s_ovp[tid] : 0u;
-      __syncthreads();
-      if (tid == 0) s_novf = 0;
-      while (__syncthreads_or(pend)) {
-        if (pend) {
-          const uint32_t old = atomicAdd(&s_fill[pp], 1u);
-          if ((old & 0xffffu) < kStageSlots) {
-            s_stage[pp * kStageSlots + ring(old >> 16, old & 0xffffu)] = rec;
-            pend = false;
-          }
-        }
-        __syncthreads();
-        flush_all();
-      }
+    if (flushed < rounds) {
+      flush_all((rounds - 1) & 1, true);
+      flushed = rounds;
     }
   };
   auto stage_pos = [&](uint64_t k) -> int64_t { return P.base_off + (int64_t)(k * STAGE); };
@@ -723,11 +735,14 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     const uint32_t old = atomicAdd(&s_fill[pp], 1u);
     if ((old & 0xffffu) < kStageSlots) {
       s_stage[pp * kStageSlots + ring(old >> 16, old & 0xffffu)] = key4(lo, hi);
+      if ((old & 0xffffu) == kChunkRec - 1)  // this record fills a chunk: list the partition
+        s_full[rounds & 1][atomicAdd(&s_nfull[rounds & 1], 1u)] = (uint16_t)pp;
     } else {
-      const uint32_t o = atomicAdd(&s_novf, 1u);
+      const uint32_t L = rounds & 1;
+      const uint32_t o = atomicAdd(&s_novf[L], 1u);
       if (o < kOverflow) {
-        s_ovf[o] = key4(lo, hi);
-        s_ovp[o] = (uint16_t)pp;
+        s_ovf[L][o] = key4(lo, hi);
+        s_ovp[L][o] = (uint16_t)pp;
       } else {
         atomicAdd(&s_stat[1], 1u);
         table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
@@ -758,13 +773,15 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     bo2 = doc_start(k + 2);
 
     // ---- 1. fold + classify; document starts in [ls, le] ---------------------------------
+    // an interior stage (inside [R0, R1), no document start in it or at its end, the next
+    // 16 bytes inside too) needs no range cuts and no boundary bits
+    const uint64_t nbk = c1 - c0;
+    const bool plain = ls >= R0 && le + 16 <= R1 && nbk == 0 && nb1 == 0;
     uint32_t w16;
     const uint4 g = classify16(cur, &w16);
-    const int64_t p = ls + tid * 16;
-    w16 = cut16(w16, p, R0, R1);
+    if (!plain) w16 = cut16(w16, ls + tid * 16, R0, R1);
     s_txt4[tid] = g;
     s_wm[tid] = (uint16_t)w16;
-    const uint64_t nbk = c1 - c0;
     if ((uint64_t)tid < nbk) {
       const uint64_t rel = bo0 - (uint64_t)ls;
       atomicOr(&s_bnd[rel >> 5], 1u << (rel & 31));
@@ -773,7 +790,12 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
       const uint64_t rel = P.offsets[c0 + j] - (uint64_t)ls;
       atomicOr(&s_bnd[rel >> 5], 1u << (rel & 31));
     }
-    if (tid == 0) {
+    if (tid == 0 && plain) {
+      uint32_t nw;
+      s_txt4[BLOCK] = classify16(nx, &nw);
+      s_next_w = nw & 1u;
+      s_next_run = (uint32_t)__builtin_ctz(~nw | 0x10000u);
+    } else if (tid == 0) {
       // the next stage's first 16 bytes: a word running over the stage end finishes there
       uint32_t nw;
       s_txt4[BLOCK] = classify16(nx, &nw);
@@ -800,8 +822,8 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     // ---- 2. start / last masks, compaction --------------------------------------------
     const uint32_t prev = tid > 0 ? (s_wm[tid - 1] >> 15) : s_carry[(k & 1) ^ 1];
     const uint32_t next = tid < BLOCK - 1 ? (s_wm[tid + 1] & 1u) : s_next_w;
-    const uint32_t bnd = (s_bnd[tid >> 1] >> ((tid & 1) * 16)) & 0xffffu;
-    const uint32_t bnext = (s_bnd[(tid + 1) >> 1] >> (((tid + 1) & 1) * 16)) & 1u;
+    const uint32_t bnd = plain ? 0u : (s_bnd[tid >> 1] >> ((tid & 1) * 16)) & 0xffffu;
+    const uint32_t bnext = plain ? 0u : (s_bnd[(tid + 1) >> 1] >> (((tid + 1) & 1) * 16)) & 1u;
     const uint32_t wprev = ((w16 << 1) | prev) & 0xffffu;
     const uint32_t start16 = w16 & (~wprev | bnd);
     const uint32_t wnext = (w16 >> 1) | (next << 15);
@@ -815,7 +837,8 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     uint32_t rank0;
     const uint32_t total = compact_starts<BLOCK>(start16, s_wsum, s_starts, kStartCap, &rank0);
     tokens += (tid == 0) ? total : 0u;
-    for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
+    if (!plain)
+      for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
     const uint32_t next_run = s_next_run;
 
     // ---- 3. tokens in rounds of BLOCK; staged chunks leave after each round. Document
@@ -826,15 +849,17 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
         write_starts(start16, rank0, w0, kStartCap, s_starts);
         __syncthreads();
       }
+      // one token round per window: each thread takes its tokens back to back. The full-list
+      // the last flush read is emptied for the flush after this round (its carry-overs go
+      // to the other list, which this round fills)
+      if (tid == 0 && flushed > 0) s_nfull[(flushed - 1) & 1] = 0;
       const uint32_t wend = min(total, w0 + kStartCap);
-      for (uint32_t t0 = w0; t0 < wend; t0 += BLOCK) {
-        const uint32_t t = t0 + tid;
-        if (t < wend) token(t - w0, ls, c1, next_run);
+      for (uint32_t t = w0 + tid; t < wend; t += BLOCK) token(t - w0, ls, c1, next_run);
+      __syncthreads();
+      ++rounds;
+      if (w0 + kStartCap < total) {  // the stage's last flush waits for the next stage
+        flush_round();
         __syncthreads();
-        if (t0 + BLOCK < wend || w0 + kStartCap < total) {  // the last round's flush waits
-          flush_round();
-          __syncthreads();
-        }
       }
     }
   }
@@ -843,6 +868,15 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   __syncthreads();
   flush_round();
   __syncthreads();
+  // staging the last overflow records can fill a chunk again: those partitions are listed
+  uint32_t Lc = rounds & 1;
+  while (__syncthreads_or(s_nfull[Lc] > 0)) {
+    if (tid == 0) s_nfull[Lc ^ 1] = 0;
+    __syncthreads();
+    flush_all(Lc, false);
+    __syncthreads();
+    Lc ^= 1;
+  }
   if (tid < (int)kParts) {
     // the last (partial) chunk; s_bpos is a multiple of kChunkRec and n < kChunkRec: it fits
     const uint32_t f = s_fill[tid], head = f >> 16, n = f & 0xffffu;

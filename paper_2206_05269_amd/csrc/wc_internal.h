@@ -35,7 +35,7 @@ constexpr uint32_t kParts = 256;         // partitions of the spilled records
 constexpr uint32_t kStageSlots = 12;     // records staged per partition in LDS
 constexpr uint32_t kChunkRec = 8;        // records per write to the arena (128 bytes)
 constexpr uint32_t kBlockRec = 256;      // records per arena block (4 KiB)
-constexpr uint32_t kOverflow = 256;      // records of one stage that found their staging full
+constexpr uint32_t kOverflow = 128;      // records of one token round that found their ring full
 constexpr uint32_t kDictMax = 2560;      // hot-word dictionary capacity (words)
 constexpr uint32_t kMapBlock = 1024;     // pass-1 workgroup
 constexpr uint32_t kGlobalStage = kMapBlock * 16;  // bytes scanned per pass-1 stage
