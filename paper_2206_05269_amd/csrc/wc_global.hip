@@ -623,21 +623,24 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
         atomicAdd(&s_stat[1], 1u);
         insert_record(rec);
       }
-      if (r == 0) {  // after the 8 reads above (same wave, program order)
-        const uint32_t nh = ring(head, kChunkRec);
-        uint32_t nc = n - kChunkRec;
-        for (uint32_t i = 0; i < novf; ++i) {
-          if (s_ovp[L][i] != q) continue;
-          if (nc < kStageSlots) {
-            s_stage[q * kStageSlots + ring(nh, nc)] = s_ovf[L][i];
-            ++nc;
-          } else {
-            atomicAdd(&s_stat[1], 1u);
-            insert_record(s_ovf[L][i]);
-          }
+      // The 8 lanes of q are in one wave: the first rewrites q's ring state after all 8 have
+      // read it; then each lane stages q's records from every 8th overflow entry.
+      const uint32_t nh = ring(head, kChunkRec);
+      if (r == 0) s_fill[q] = (nh << 16) | (n - kChunkRec);
+      for (uint32_t i = r; i < novf; i += kChunkRec) {
+        if (s_ovp[L][i] != q) continue;
+        const uint32_t c = atomicAdd(&s_fill[q], 1u) & 0xffffu;
+        if (c < kStageSlots) {
+          s_stage[q * kStageSlots + ring(nh, c)] = s_ovf[L][i];
+        } else {
+          atomicSub(&s_fill[q], 1u);
+          atomicAdd(&s_stat[1], 1u);
+          insert_record(s_ovf[L][i]);
         }
-        s_fill[q] = (nh << 16) | nc;
-        if (nc >= kChunkRec) s_full[L ^ 1][atomicAdd(&s_nfull[L ^ 1], 1u)] = (uint16_t)q;
+      }
+      if (r == 0) {
+        if ((s_fill[q] & 0xffffu) >= kChunkRec)
+          s_full[L ^ 1][atomicAdd(&s_nfull[L ^ 1], 1u)] = (uint16_t)q;
         if (b != kNone) {
           uint32_t nbp = bp + kChunkRec;
           if (nbp == kBlockRec) {
