@@ -63,7 +63,7 @@ typedef int32_t wc_status;
 #define WC_DEBUG_NO_LDS 2u  /* skip the LDS table: every token goes to the global table */
 #define WC_DEBUG_DIRECT 4u  /* global mode: one-pass kernel (LDS table + global atomics) */
 #define WC_DEBUG_SPILL  8u  /* global mode: two-pass kernels (LDS table + partitioned spill)
-                               even for small inputs; by default they run from 64 MiB up */
+                               even for small inputs; by default they run from 256 MiB up */
 
 /* Launch tuning; a zero field takes the library default. */
 typedef struct wc_tuning {

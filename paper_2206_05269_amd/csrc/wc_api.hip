@@ -18,7 +18,7 @@ constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultLds = 2048;
 constexpr uint32_t kDefaultBlock = 512;
 constexpr uint32_t kReduceLds = 5632;         // pass-2 LDS entries (110 KiB + 32 KiB of slots)
-constexpr uint64_t kSpillMinBytes = 64ull << 20;
+constexpr uint64_t kSpillMinBytes = 256ull << 20;  // two-pass global count from this size
 constexpr uint64_t kMaxWgBytes = 1ull << 31;  // text per pass-1 workgroup (32-bit LDS counts)
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -278,11 +278,11 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
     L->dict_cap = std::min<uint32_t>(o->tuning && o->tuning->lds_entries ? tu.lds : kDictMax,
                                      kDictMax);
     // Each workgroup owns J interleaved blocks of every partition: room for one record per
-    // 16 bytes of text spread evenly, plus one block; a quarter more is handed out on demand
-    // to workgroups that need it. A partition that still runs out counts in the global table.
+    // 16 bytes of text spread evenly; a quarter more is handed out on demand to workgroups
+    // that need it. A partition that still runs out counts in the global table.
     const uint64_t blk_bytes = (uint64_t)kBlockRec * 16;
     const uint64_t per = grid * kParts * kBlockRec;  // records per static round of blocks
-    const uint64_t J = (len / 16 + per - 1) / per + 1;
+    const uint64_t J = std::max<uint64_t>(1, (len / 16 + per - 1) / per);
     const uint64_t S = J * grid;
     L->static_blocks = (uint32_t)S;
     L->R = (uint32_t)(S + std::max<uint64_t>(64, S / 4));
