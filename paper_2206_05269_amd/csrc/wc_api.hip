@@ -285,7 +285,9 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
     const uint64_t J = std::max<uint64_t>(1, (len / 16 + per - 1) / per);
     const uint64_t S = J * grid;
     L->static_blocks = (uint32_t)S;
-    L->R = (uint32_t)(S + std::max<uint64_t>(64, S / 4));
+    const uint64_t R = S + std::max<uint64_t>(64, S / 4);
+    if ((uint64_t)kParts * R >= (1ull << 32)) return false;  // block indices are 32-bit
+    L->R = (uint32_t)R;
     L->arena = B.take<uint4>((uint64_t)kParts * L->R * blk_bytes);
     L->cursor = B.take<uint32_t>(kParts * 4);
     L->fill = B.take<uint16_t>((uint64_t)kParts * L->R * 2);
@@ -335,6 +337,7 @@ wc_status finish_flags(const Header& h) {
   if (h.flags & kFlagTableFull) return WC_ETABLEFULL;
   if (h.flags & kFlagWordCap) return WC_ENOMEM;
   if (h.flags & kFlagCountOverflow) return WC_EOVERFLOW;
+  if (h.flags & kFlagStall) return WC_EDEVICE;
   return WC_OK;
 }
 
@@ -548,7 +551,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
   Header h;
   HIPCHK(hipMemcpyAsync(&h, L.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (h.flags & (kFlagBadOffsets | kFlagTableFull)) return finish_flags(h);
+  if (h.flags & (kFlagBadOffsets | kFlagTableFull | kFlagStall)) return finish_flags(h);
 
   memset(out, 0, sizeof(*out));
   out->n_entries = h.n_entries;

@@ -38,6 +38,7 @@ constexpr uint32_t kFlagTableFull = 1u;
 constexpr uint32_t kFlagBadOffsets = 2u;
 constexpr uint32_t kFlagWordCap = 4u;
 constexpr uint32_t kFlagCountOverflow = 8u;
+constexpr uint32_t kFlagStall = 16u;  // a bounded wait inside a kernel gave up (internal error)
 
 struct Slot {
   uint64_t key;

@@ -6,22 +6,21 @@
 // byte rate of the scan. So:
 //
 //   dictionary: a sample of the text (kSampleStages stages of 8 KiB spread evenly over it) is
-//     counted, and the most frequent words (up to kDictMax) become a read-only dictionary:
-//     two-choice buckets of 4 tagged slots. A word is found in at most two 16-byte bucket
-//     reads and one key read, with no insertion, eviction or probe loop.
-//   pass 1 (global_map_kernel): scan the text; a dictionary word is counted in LDS; any other
-//     token becomes a 16-byte record (its packed bytes) in one of 256 partitions chosen by a
-//     hash of the word. Records wait in LDS (kStageSlots per partition) and leave in aligned
-//     128-byte chunks into 4 KiB blocks of the partition's arena region, so the spill is
-//     sequential full-line writes. The next block is requested half a block ahead, so its
-//     atomic never stalls a flush.
+//     counted, and the most frequent words (up to kDictMax) become a read-only dictionary of
+//     8-slot tagged buckets. A word is found with one read of its bucket's tags and indices and
+//     one key read, with no insertion, eviction or probe loop.
+//   pass 1 (global_map_kernel): scan the text, each wave on its own 1 KiB stripes; a dictionary
+//     word is counted in LDS; any other token becomes a 16-byte record (its packed bytes) in one
+//     of 256 partitions chosen by a hash of the word. Records wait in an LDS ring per partition
+//     and leave in aligned 128-byte chunks into 4 KiB blocks of the partition's arena region,
+//     so the spill is sequential full-line writes.
 //   pass 2 (global_reduce_kernel): one workgroup per partition reads that partition's
 //     records, sums them in an LDS table and adds each distinct word once to the global
 //     table; it also totals the dictionary hits of its share of dictionary words.
 //
 // Counts are exact whatever the dictionary holds: it only decides where a word is summed.
-// Words longer than 16 bytes, and anything a bounded structure cannot take (a full overflow
-// list, an exhausted arena region, a full pass-2 table), go to the global table directly.
+// Words longer than 16 bytes, and anything a bounded structure cannot take (an exhausted arena
+// region, a full pass-2 table), go to the global table directly.
 #include "wc_internal.h"
 
 namespace wc {
@@ -52,18 +51,22 @@ WC_DEV uint64_t short_key_g(uint64_t lo, uint64_t hi, uint64_t key_mask) {
   return finish_key(fnv_packed(lo, hi, packed_len(lo, hi)), key_mask);
 }
 
-// Index of the word in the dictionary, or -1: one 8-byte read of the bucket's tags, a SWAR
-// match of the tag against all 8 (a flagged byte above a true match may be spurious; the key
-// compare settles every candidate), and a key read per candidate.
+// Index of the word in the dictionary, or -1: one 8-byte read of the bucket's tags and, at the
+// same time, one 16-byte read of its 8 key indices; a SWAR match of the tag against all 8 (a
+// flagged byte above a true match may be spurious; the key compare settles every candidate),
+// and a key read per candidate.
 WC_DEV int dict_find(const uint64_t* tags8, const uint16_t* idx, const uint4* keys, uint32_t nb,
                      uint64_t lo, uint64_t hi, uint32_t h) {
   const uint32_t b = dict_bucket(h, nb);
-  const uint64_t x = tags8[b] ^ (0x0101010101010101ull * dict_tag(h));
+  const uint64_t t8 = tags8[b];
+  const uint4 row = ((const uint4*)idx)[b];
+  const uint64_t x = t8 ^ (0x0101010101010101ull * dict_tag(h));
   uint64_t z = (x - 0x0101010101010101ull) & ~x & 0x8080808080808080ull;
   const uint4 want = key4(lo, hi);
   while (z) {
     const uint32_t j = (uint32_t)(__ffsll((unsigned long long)z) - 1) >> 3;
-    const uint32_t i = idx[b * 8 + j];
+    const uint32_t d = j < 4 ? (j < 2 ? row.x : row.y) : (j < 6 ? row.z : row.w);
+    const uint32_t i = (j & 1) ? d >> 16 : d & 0xffffu;
     const uint4 k = keys[i];
     if (k.x == want.x && k.y == want.y && k.z == want.z && k.w == want.w) return (int)i;
     z &= z - 1;
@@ -499,60 +502,113 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
 // ---------------------------------------------------------------------------------------
 // pass 1
 // ---------------------------------------------------------------------------------------
+constexpr int kMapWaves = kMapBlock / 64;
+constexpr uint32_t kLongEnd = 0x7ffu;                    // word end not within the staged bytes
+constexpr uint32_t kBndWords = kStripeText / 32 + 1;     // document-start bits of a stripe
+constexpr uint32_t kSpinLimit = 1u << 24;                // rounds of one wait before giving up
+
 size_t global_map_dyn(uint32_t dict_cap) {
-  return (size_t)kParts * kStageSlots * 16 + (size_t)(kMapBlock + 2) * 16 +
-         (size_t)kDictBuckets * (8 + 16) + (size_t)dict_cap * 20 + (size_t)kGlobalStage;
+  return (size_t)kParts * kStageSlots * 16 + (size_t)kMapWaves * kStripeText +
+         (size_t)kDictBuckets * (8 + 16) + (size_t)dict_cap * 20 +
+         (size_t)kMapWaves * kWaveStarts * 4;
 }
 
-// One workgroup of BLOCK threads scans a contiguous range of STAGE-byte stages, 16 bytes per
-// thread per stage. Per stage: classify and mark document starts; word start / last masks and
-// a block-wide compaction of the starts; tokens in rounds of BLOCK, each round followed by the
-// flush of full 128-byte chunks from the partition staging.
+// 4 bytes of the logical text at p (p + base alignment keeps them in one aligned dword); bytes
+// outside [0, len) read as spaces.
+WC_DEV uint32_t load_text4(const uint8_t* corpus, uint64_t len, int64_t p) {
+  if (p >= 0 && p + 4 <= (int64_t)len) return *(const uint32_t*)(corpus + p);
+  uint32_t w = 0x20202020u;
+  for (int j = 0; j < 4; ++j) {
+    const int64_t q = p + j;
+    if (q >= 0 && q < (int64_t)len)
+      w = (w & ~(0xffu << (8 * j))) | ((uint32_t)corpus[q] << (8 * j));
+  }
+  return w;
+}
+
+// (start, end) of each word starting in this lane's 16 bytes, in text order, for the ranks in
+// [w0, w0 + kWaveStarts): end from this lane's last-byte mask, else from the next lane's (nl),
+// else kLongEnd (the word runs past the next lane's bytes: longer than 16 bytes).
+WC_DEV void write_pairs(uint32_t m, uint32_t last16, uint32_t nl, uint32_t rank, uint32_t w0,
+                        uint32_t* pairs) {
+  const uint32_t pos0 = (threadIdx.x & 63) * 16;
+  while (m) {
+    const uint32_t j = __ffs(m) - 1;
+    if (rank - w0 < kWaveStarts) {
+      const uint32_t bits = last16 >> j;
+      const uint32_t e = bits ? pos0 + j + __ffs(bits) - 1
+                              : (nl ? pos0 + 16 + __ffs(nl) - 1 : kLongEnd);
+      pairs[rank - w0] = (pos0 + j) | (e << 16);
+    }
+    ++rank;
+    m &= m - 1;
+  }
+}
+
+// Orders this wave's LDS accesses around the point in the compiler (the hardware keeps one
+// wave's LDS operations in order).
+WC_DEV void wave_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// One workgroup of BLOCK threads scans a contiguous range of STAGE-byte stages; wave v takes
+// the v-th 1 KiB stripe of every stage and runs on its own, with no workgroup barrier until
+// the range ends. Per stripe: classify 16 bytes per lane (plus the 16 bytes after the stripe,
+// for the word that crosses its end, and the byte before it), word start / end masks, a
+// wave-wide compaction of the (start, end) pairs, and one token per lane per round: counted in
+// the dictionary, or staged as a record in its partition's ring, or (longer than 16 bytes)
+// counted in the global table.
+//
+// Partition rings. s_fill[p] = (head << 16) | count: records carry 16-bit tickets; head is the
+// ticket of the oldest record held, count the records reserved since. A token reserves ticket
+// head + count with one LDS atomic; with count < kStageSlots its slot (ticket mod kStageSlots)
+// is free and it writes the record at once, otherwise it waits until head has come within
+// kStageSlots of its ticket. The lane holding the last ticket of a chunk of 8 owns the chunk;
+// after each round of tokens a wave sends out the chunks its lanes own, 8 lanes per chunk (one
+// aligned 128-byte write). A chunk leaves when head has reached it and its 8 records are
+// written (a record's first dword is never 0); its slots are zeroed, then head moves on by 8.
+// Chunks of a partition so leave in ticket order, and the oldest chunk can always leave: its
+// records never wait for a slot, and a wave never waits without serving the chunks it owns.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
+  constexpr int NW = BLOCK / 64;
   constexpr int STAGE = BLOCK * 16;
   constexpr uint32_t kNone = 0xffffffffu;
-  constexpr uint32_t kStartCap = STAGE / 2;  // word starts held at once (u16 each)
-  static_assert(STAGE == (int)kGlobalStage, "stage size shared with the host layout");
-  static_assert(BLOCK >= (int)kParts && BLOCK >= (int)kOverflow && BLOCK >= (int)kSdWin + 3,
-                "one thread per partition, overflow entry and cached stage entry");
+  constexpr uint32_t kRingMask = kStageSlots - 1;
+  static_assert(STAGE == (int)kGlobalStage && NW * (int)kStripe == STAGE,
+                "a stage is one stripe per wave");
+  static_assert(NW == kMapWaves && BLOCK >= (int)kParts, "one thread per partition at the end");
+  static_assert((kStageSlots & kRingMask) == 0 && kStageSlots >= 2 * kChunkRec &&
+                    65536 % kBlockRec == 0 && kWaveStarts == 128,
+                "16-bit tickets wrap at a multiple of the ring and the block; a round takes two "
+                "tokens per lane");
   extern __shared__ __align__(16) uint8_t s_dyn[];
-  __shared__ uint16_t s_wm[BLOCK];
-  __shared__ uint16_t s_last[BLOCK + 1];
-  __shared__ uint32_t s_bnd[STAGE / 32 + 2];
   __shared__ uint32_t s_fill[kParts];
-  __shared__ uint32_t s_blk[kParts];
-  __shared__ uint16_t s_bpos[kParts];
-  __shared__ uint4 s_ovf[2][kOverflow];    // by token-round parity
-  __shared__ uint16_t s_ovp[2][kOverflow];
-  __shared__ uint64_t s_sd[kSdWin + 3];
-  __shared__ uint32_t s_wsum[BLOCK / 64];
-  __shared__ uint32_t s_novf[2], s_next_w, s_next_run;
-  __shared__ uint16_t s_full[2][kParts];    // partitions holding a full chunk, by round parity
-  __shared__ uint32_t s_nfull[2];
-  __shared__ uint32_t s_carry[2];
+  __shared__ uint32_t s_blk[kParts];  // arena block p * R + b being filled, or kNone
+  __shared__ uint32_t s_bnd[NW][kBndWords];
+  __shared__ uint32_t s_dq[NW][8];
   __shared__ uint32_t s_stat[4];
 
   const uint32_t D = P.dict_cap;
-  uint4* s_stage = (uint4*)s_dyn;                         // [kParts][kStageSlots]
-  uint4* s_txt4 = s_stage + kParts * kStageSlots;         // [BLOCK + 2]
-  uint64_t* s_tags8 = (uint64_t*)(s_txt4 + (BLOCK + 2));  // [kDictBuckets]
-  uint16_t* s_idx = (uint16_t*)(s_tags8 + kDictBuckets);  // [kDictBuckets * 8]
-  uint4* s_keys = (uint4*)(s_idx + kDictBuckets * 8);     // [D]
-  uint32_t* s_cnt = (uint32_t*)(s_keys + D);              // [D]
-  uint16_t* s_starts = (uint16_t*)(s_cnt + D);            // [STAGE / 2]
-  const uint8_t* s_txt = (const uint8_t*)s_txt4;
+  uint4* s_stage = (uint4*)s_dyn;                               // [kParts][kStageSlots]
+  uint8_t* s_txt = (uint8_t*)(s_stage + kParts * kStageSlots);  // [NW][kStripeText]
+  uint64_t* s_tags8 = (uint64_t*)(s_txt + NW * kStripeText);    // [kDictBuckets]
+  uint16_t* s_idx = (uint16_t*)(s_tags8 + kDictBuckets);        // [kDictBuckets * 8]
+  uint4* s_keys = (uint4*)(s_idx + kDictBuckets * 8);           // [D]
+  uint32_t* s_cnt = (uint32_t*)(s_keys + D);                    // [D]
+  uint32_t* s_pairs = s_cnt + D;                                // [NW][kWaveStarts]
 
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   Header* hdr = P.hdr;
   if (ld_relaxed32(&hdr->flags) & kFlagBadOffsets) return;
   const uint64_t st0 = (uint64_t)blockIdx.x * P.stages_per_wg;
   const uint64_t st1 = min(st0 + P.stages_per_wg, P.n_stages);
   const uint64_t n_stages = P.n_stages;
-  const int64_t len = (int64_t)P.len;
   const int64_t R0 = (int64_t)P.offsets[0], R1 = (int64_t)P.offsets[P.n_docs];
 
-  // dictionary into LDS
   const uint32_t nd = P.dict->n, nb = P.dict->nb;
   for (uint32_t i = tid; i < nb; i += BLOCK) s_tags8[i] = P.dict->tags[i];
   for (uint32_t i = tid; i < nb * 8; i += BLOCK) s_idx[i] = P.dict->idx[i];
@@ -560,33 +616,29 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     s_keys[i] = P.dict->keys[i];
     s_cnt[i] = 0;
   }
-  for (uint32_t p = tid; p < kParts; p += BLOCK) s_fill[p] = 0;
-  if (tid < 2) {
-    s_novf[tid] = 0;
-    s_nfull[tid] = 0;
-  }
-  if (tid < 4) s_stat[tid] = 0;
-  for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
-
-  // Partition staging is a ring of kStageSlots records per partition; s_fill[p] packs the
-  // ring head (high 16 bits) and the number of records held (low 16 bits), so a token reserves
-  // its slot with one LDS atomic and a flush moves no records. s_blk[p] is the partition's
-  // current arena block (kNone once the partition's region is exhausted), s_bpos[p] the
-  // records already in it. This workgroup's j-th own block of a partition is j * G + w; past
-  // its S / G own blocks it takes blocks from [S, R) with an atomic.
+  for (uint32_t i = tid; i < kParts * kStageSlots; i += BLOCK) s_stage[i] = make_uint4(0, 0, 0, 0);
+  // This workgroup's j-th own block of a partition is j * G + w; past its S / G own blocks it
+  // takes blocks from [S, R) with an atomic. A block is filled completely before the next, so
+  // the position in the current block is head mod kBlockRec.
   const uint32_t G = gridDim.x, w = blockIdx.x;
   for (uint32_t p = tid; p < kParts; p += BLOCK) {
-    s_blk[p] = w < P.S ? w : kNone;
-    s_bpos[p] = 0;
+    s_fill[p] = 0;
+    s_blk[p] = w < P.S ? p * P.R + w : kNone;
   }
-  auto ring = [](uint32_t head, uint32_t k) -> uint32_t {
-    const uint32_t x = head + k;
-    return x >= kStageSlots ? x - kStageSlots : x;
-  };
-  auto next_block = [&](uint32_t p, uint32_t b) -> uint32_t {
-    if (b + G < P.S) return b + G;
+  for (uint32_t i = tid; i < NW * kBndWords; i += BLOCK) (&s_bnd[0][0])[i] = 0;
+  if (tid < 4) s_stat[tid] = 0;
+  __syncthreads();
+
+  uint8_t* const my_txt = s_txt + wv * kStripeText;
+  uint32_t* const my_bnd = s_bnd[wv];
+  uint32_t* const my_pairs = s_pairs + wv * kWaveStarts;
+
+  // the block after block gb (= p * R + b) of partition p, or kNone
+  auto next_block = [&](uint32_t p, uint32_t gb) -> uint32_t {
+    const uint32_t b = gb - p * P.R;
+    if (b + G < P.S) return gb + G;
     const uint32_t d = P.S + atomicAdd(&P.cursor[p], 1u);
-    return d < P.R ? d : kNone;
+    return d < P.R ? p * P.R + d : kNone;
   };
   auto insert_record = [&](const uint4 r) {
     const uint64_t lo = (uint64_t)r.x | ((uint64_t)r.y << 32);
@@ -594,314 +646,314 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
                         short_id(lo, hi, 0), 1, hdr, P.occ_limit);
   };
-  // Every partition listed in s_full[L] holds a full chunk and sends it out: 8 lanes per
-  // partition (one record each, in one wave); the first of the 8 then advances the ring and
-  // the block, and stages the partition's records from overflow list L (a partition overflows
-  // only with a full ring, so it is listed now and has room). A partition still holding a
-  // full chunk is listed for the next round. Lists L ^ 1 were read by the previous flush and
-  // are cleared for the next round.
-  auto flush_all = [&](uint32_t L, bool with_ovf) {
-    const uint32_t novf = with_ovf ? min(s_novf[L], kOverflow) : 0u;
-    const uint32_t nfull = s_nfull[L];
-    if (tid == 0) {
-      s_novf[L ^ 1] = 0;
-      s_stat[2] += novf;
+  // first document start after pos (offsets[n_docs], the end of the range, is one)
+  auto doc_limit = [&](uint64_t pos) -> uint64_t {
+    uint64_t a = 1, b = P.n_docs;
+    while (a < b) {
+      const uint64_t m = (a + b) >> 1;
+      if (P.offsets[m] > pos) b = m;
+      else a = m + 1;
     }
-    // s_full[L ^ 1] collects partitions for the next round; it was emptied before this
-    // round's tokens ran
-    for (uint32_t task = tid; task < nfull * kChunkRec; task += BLOCK) {
-      const uint32_t q = s_full[L][task / kChunkRec], r = task % kChunkRec;
-      const uint32_t f = s_fill[q];
-      const uint32_t head = f >> 16;
-      uint32_t n = f & 0xffffu;
-      n = n < kStageSlots ? n : kStageSlots;  // reservations past the end overflowed
-      const uint32_t b = s_blk[q], bp = s_bpos[q];
-      const uint4 rec = s_stage[q * kStageSlots + ring(head, r)];
-      if (b != kNone) {
-        P.arena[((uint64_t)q * P.R + b) * kBlockRec + bp + r] = rec;
-      } else {
-        atomicAdd(&s_stat[1], 1u);
-        insert_record(rec);
-      }
-      // The 8 lanes of q are in one wave: the first rewrites q's ring state after all 8 have
-      // read it; then each lane stages q's records from every 8th overflow entry.
-      const uint32_t nh = ring(head, kChunkRec);
-      if (r == 0) s_fill[q] = (nh << 16) | (n - kChunkRec);
-      for (uint32_t i = r; i < novf; i += kChunkRec) {
-        if (s_ovp[L][i] != q) continue;
-        const uint32_t c = atomicAdd(&s_fill[q], 1u) & 0xffffu;
-        if (c < kStageSlots) {
-          s_stage[q * kStageSlots + ring(nh, c)] = s_ovf[L][i];
-        } else {
-          atomicSub(&s_fill[q], 1u);
-          atomicAdd(&s_stat[1], 1u);
-          insert_record(s_ovf[L][i]);
-        }
-      }
-      if (r == 0) {
-        if ((s_fill[q] & 0xffffu) >= kChunkRec)
-          s_full[L ^ 1][atomicAdd(&s_nfull[L ^ 1], 1u)] = (uint16_t)q;
-        if (b != kNone) {
-          uint32_t nbp = bp + kChunkRec;
-          if (nbp == kBlockRec) {
-            P.fill[(uint64_t)q * P.R + b] = (uint16_t)kBlockRec;
-            s_blk[q] = next_block(q, b);
-            nbp = 0;
-          }
-          s_bpos[q] = (uint16_t)nbp;
-        }
-      }
-    }
-  };
-  uint32_t rounds = 0, flushed = 0;  // token rounds done / flushed (uniform)
-  // after a token round (all threads, behind a barrier)
-  auto flush_round = [&]() {
-    if (flushed < rounds) {
-      flush_all((rounds - 1) & 1, true);
-      flushed = rounds;
-    }
-  };
-  auto stage_pos = [&](uint64_t k) -> int64_t { return P.base_off + (int64_t)(k * STAGE); };
-  const uint4 blank = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
-  auto load16 = [&](uint64_t k) -> uint4 {
-    return load_text16(P.corpus, P.len, stage_pos(k) + tid * 16);
+    return P.offsets[a];
   };
 
-  // stage -> first document starting at or after it, cached kSdWin stages at a time
-  uint64_t sd_base = st0;
-  for (uint32_t i = tid; i < kSdWin + 3; i += BLOCK)
-    s_sd[i] = P.stage_doc[min(st0 + i, n_stages)];
-  if (tid == 0) {
-    int64_t q = stage_pos(st0) - 1;
-    s_carry[(st0 & 1) ^ 1] =
-        (q >= R0 && q < R1 && q >= 0 && q < len && is_word_byte(P.corpus[q])) ? 1u : 0u;
-  }
-  __syncthreads();
-  // document starts of a stage (thread i holds the i-th)
-  auto doc_start = [&](uint64_t k) -> uint64_t {
-    if (k >= n_stages) return ~0ull;
-    const uint64_t c0 = s_sd[k - sd_base], c1 = s_sd[k + 1 - sd_base];
-    return (uint64_t)tid < c1 - c0 ? P.offsets[c0 + tid] : ~0ull;
-  };
-  uint64_t bo1 = doc_start(st0), bo2 = doc_start(st0 + 1), bo0;
+  uint32_t spilled = 0, direct = 0, waits = 0;
+  bool stalled = false;
+  // Per lane and token slot (a: tokens t < 64 of a round, b: t >= 64): a record waiting for a
+  // slot (pend: partition, ticket, record) and a chunk this lane owns ((partition << 16) | last
+  // ticket). Chunks are sent out in the same round.
+  bool pend_a = false, pend_b = false, own_a = false, own_b = false;
+  uint32_t pa_p = 0, pa_t = 0, pb_p = 0, pb_t = 0, oval_a = 0, oval_b = 0;
+  uint32_t pa0 = 0, pa1 = 0, pa2 = 0, pa3 = 0, pb0 = 0, pb1 = 0, pb2 = 0, pb3 = 0;
 
-  uint64_t tokens = 0;
-  uint32_t spilled = 0;  // records this thread sent to the partitions
-  // one token: count it in the dictionary, stage it as a record, or (longer than 16 bytes)
-  // count it in the global table
-  auto token = [&](uint32_t t, int64_t ls, uint64_t c1, uint32_t next_run) {
-    const uint32_t s = s_starts[t];
-    uint32_t q = s >> 4;
-    const uint32_t bits = (uint32_t)s_last[q] >> (s & 15);
-    uint32_t e;
-    bool crosses = false;
-    if (bits) {
-      e = s + __ffs(bits) - 1;
-    } else {
-      ++q;
-      while (q < BLOCK && s_last[q] == 0) ++q;
-      if (q < BLOCK) {
-        e = q * 16 + __ffs(s_last[q]) - 1;
+  // One pass over up to 8 owned chunks (a-slot owners first, then b-slot owners), 8 lanes (one
+  // record each) per chunk. Owned chunks that are not ready stay owned.
+  auto flush_pass = [&](uint64_t oma, uint64_t omb) {
+    const uint32_t na = (uint32_t)__popcll(oma);
+    const uint32_t ia = __builtin_amdgcn_mbcnt_hi((uint32_t)(oma >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)oma, 0u));
+    const uint32_t ib = na + __builtin_amdgcn_mbcnt_hi((uint32_t)(omb >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)omb, 0u));
+    if (own_a && ia < 8) s_dq[wv][ia] = oval_a;
+    if (own_b && ib < 8) s_dq[wv][ib] = oval_b;
+    wave_sync();
+    const uint32_t nc = min(na + (uint32_t)__popcll(omb), 8u);
+    const uint32_t g = lane >> 3, j = lane & 7;
+    bool ok = false;
+    uint32_t q = 0, start = 0, slot = 0;
+    uint4 r4 = make_uint4(0, 0, 0, 0);
+    if (g < nc) {
+      const uint32_t v = s_dq[wv][g];
+      q = v >> 16;
+      start = (v - (kChunkRec - 1)) & 0xffffu;
+      // head first: once it has reached the chunk, the slots hold the chunk's records or 0
+      const uint32_t head =
+          __hip_atomic_load(&s_fill[q], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >> 16;
+      slot = q * kStageSlots + ((start + j) & kRingMask);
+      r4 = s_stage[slot];
+      ok = head == start && r4.x != 0;
+    }
+    const uint64_t okm = __ballot(ok);
+    if (g < nc && ((okm >> (8 * g)) & 0xffull) == 0xffull) {
+      const uint32_t gb = s_blk[q], bp = start & (kBlockRec - 1);
+      if (gb != kNone) {
+        P.arena[(uint64_t)gb * kBlockRec + bp + j] = r4;
       } else {
-        crosses = true;
-        e = STAGE + next_run - 1;
+        ++direct;
+        insert_record(r4);
+      }
+      s_stage[slot] = make_uint4(0, 0, 0, 0);
+      if (j == 0) {
+        if (gb != kNone && bp + kChunkRec == kBlockRec) {
+          P.fill[gb] = (uint16_t)kBlockRec;
+          s_blk[q] = next_block(q, gb);
+        }
+        wave_sync();  // the zeroed slots before the ring moves on
+        atomicAdd(&s_fill[q], (kChunkRec << 16) - kChunkRec);  // head += 8 (mod 2^16)
       }
     }
-    const uint32_t wl = e - s + 1;
-    uint64_t lo, hi;
-    if (wl <= 16 && !(crosses && next_run >= 16)) {
-      pack_word(s_txt, s, wl, &lo, &hi);
-    } else {
-      // longer than 16 bytes (or running past the bytes staged): from device memory
-      const uint64_t start = (uint64_t)(ls + s);
-      uint64_t limit = start + wl;
-      if (crosses) {
-        limit = (uint64_t)R1;
-        if (c1 <= P.n_docs && P.offsets[c1] < limit) limit = P.offsets[c1];
-      }
-      uint64_t h64;
-      const uint64_t n = scan_word(P.corpus, start, limit, &lo, &hi, &h64);
-      if (n > 16) {
-        table_insert<false>(P.table, P.mask, finish_key(h64, P.key_mask),
-                            long_id(P.corpus + start, n, 0), 1, hdr, P.occ_limit);
-        return;
-      }
+    if (own_a && ia < 8 && ((okm >> (8 * ia)) & 0xffull) == 0xffull) own_a = false;
+    if (own_b && ib < 8 && ((okm >> (8 * ib)) & 0xffull) == 0xffull) own_b = false;
+    wave_sync();  // s_dq is rewritten by the next pass
+  };
+  auto try_place = [&](bool& pend, uint32_t p, uint32_t tick, const uint4 rec) {
+    const uint32_t head =
+        __hip_atomic_load(&s_fill[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 16;
+    if (((tick - head) & 0xffffu) < kStageSlots) {
+      s_stage[p * kStageSlots + (tick & kRingMask)] = rec;
+      pend = false;
     }
-    const uint32_t h = word_hash32(lo, hi);
-    const int idx = nd ? dict_find(s_tags8, s_idx, s_keys, nb, lo, hi, h) : -1;
-    if (idx >= 0) {
-      atomicAdd(&s_cnt[idx], 1u);
-      return;
+  };
+  // Wave-uniform: places waiting records and sends out owned chunks until none is left.
+  auto serve = [&]() {
+    uint32_t spins = 0;
+    while (!stalled) {
+      if (pend_a) try_place(pend_a, pa_p, pa_t, make_uint4(pa0, pa1, pa2, pa3));
+      if (pend_b) try_place(pend_b, pb_p, pb_t, make_uint4(pb0, pb1, pb2, pb3));
+      // a chunk can leave only once the owner's own record is in it
+      const uint64_t oma = __ballot(own_a && !pend_a), omb = __ballot(own_b && !pend_b);
+      if (!__any(pend_a || pend_b || own_a || own_b)) break;
+      if (spins) __builtin_amdgcn_s_sleep(1);  // waiting on other waves
+      if (++spins >= kSpinLimit) {
+        stalled = true;
+        break;
+      }
+      if (oma | omb) flush_pass(oma, omb);
     }
-    spilled += 1;
-    const uint32_t pp = part_of(h);
-    const uint32_t old = atomicAdd(&s_fill[pp], 1u);
+    waits += spins > 1 ? spins - 1 : 0;
+  };
+  // a token that missed the dictionary: reserve its ticket, write the record if its slot is
+  // free, own the chunk it completes
+  auto stage_record = [&](uint32_t p, const uint4 rec, bool& pend, uint32_t& pp, uint32_t& pt,
+                          uint32_t& r0, uint32_t& r1, uint32_t& r2, uint32_t& r3, bool& own,
+                          uint32_t& oval) {
+    const uint32_t old = atomicAdd(&s_fill[p], 1u);
+    const uint32_t tick = ((old >> 16) + old) & 0xffffu;
     if ((old & 0xffffu) < kStageSlots) {
-      s_stage[pp * kStageSlots + ring(old >> 16, old & 0xffffu)] = key4(lo, hi);
-      if ((old & 0xffffu) == kChunkRec - 1)  // this record fills a chunk: list the partition
-        s_full[rounds & 1][atomicAdd(&s_nfull[rounds & 1], 1u)] = (uint16_t)pp;
+      s_stage[p * kStageSlots + (tick & kRingMask)] = rec;
     } else {
-      const uint32_t L = rounds & 1;
-      const uint32_t o = atomicAdd(&s_novf[L], 1u);
-      if (o < kOverflow) {
-        s_ovf[L][o] = key4(lo, hi);
-        s_ovp[L][o] = (uint16_t)pp;
-      } else {
-        atomicAdd(&s_stat[1], 1u);
-        table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
-                            short_id(lo, hi, 0), 1, hdr, P.occ_limit);
-      }
+      pend = true;
+      pp = p;
+      pt = tick;
+      r0 = rec.x;
+      r1 = rec.y;
+      r2 = rec.z;
+      r3 = rec.w;
+    }
+    if ((tick & (kChunkRec - 1)) == kChunkRec - 1) {
+      own = true;
+      oval = (p << 16) | tick;
+    }
+    ++spilled;
+  };
+  // a word longer than 16 bytes (or with its end beyond the staged bytes): from device memory,
+  // into the global table
+  auto long_token = [&](int64_t p0, uint32_t s, uint32_t e) {
+    const uint64_t start = (uint64_t)(p0 + s);
+    const uint64_t limit = e == kLongEnd ? doc_limit(start) : start + (e - s + 1);
+    uint64_t lo, hi, h64;
+    const uint64_t n = scan_word(P.corpus, start, limit, &lo, &hi, &h64);
+    if (n > 16) {
+      table_insert<false>(P.table, P.mask, finish_key(h64, P.key_mask),
+                          long_id(P.corpus + start, n, 0), 1, hdr, P.occ_limit);
+    } else {
+      table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
+                          short_id(lo, hi, 0), 1, hdr, P.occ_limit);
     }
   };
 
-  // text: this stage and the next (one past the range: the next stage's first bytes close a
-  // word that crosses the range end)
-  uint4 cur = load16(st0), nx = blank;
-  if (st0 + 1 < n_stages) nx = load16(st0 + 1);
+  // One round: pairs t and t + 64 of this wave's list (t = lane), for those below nw.
+  auto token_round = [&](uint32_t nw, int64_t p0) {
+    const uint32_t ta = lane, tb = lane + 64;
+    const uint32_t pra = ta < nw ? my_pairs[ta] : 0u, prb = tb < nw ? my_pairs[tb] : 0u;
+    const uint32_t sa = pra & 0xffffu, ea = pra >> 16, sb = prb & 0xffffu, eb = prb >> 16;
+    const bool longa = ta < nw && (ea == kLongEnd || ea - sa >= 16);
+    const bool longb = tb < nw && (eb == kLongEnd || eb - sb >= 16);
+    const bool fa = ta < nw && !longa, fb = tb < nw && !longb;
+    if (longa) long_token(p0, sa, ea);
+    if (longb) long_token(p0, sb, eb);
+    uint64_t loa = 0, hia = 0, lob = 0, hib = 0;
+    if (fa) pack_word(my_txt, sa, ea - sa + 1, &loa, &hia);
+    if (fb) pack_word(my_txt, sb, eb - sb + 1, &lob, &hib);
+    const uint32_t ha = word_hash32(loa, hia), hb = word_hash32(lob, hib);
+    const int ia = fa && nd ? dict_find(s_tags8, s_idx, s_keys, nb, loa, hia, ha) : -1;
+    const int ib = fb && nd ? dict_find(s_tags8, s_idx, s_keys, nb, lob, hib, hb) : -1;
+    if (ia >= 0) atomicAdd(&s_cnt[ia], 1u);
+    if (ib >= 0) atomicAdd(&s_cnt[ib], 1u);
+    if (fa && ia < 0)
+      stage_record(part_of(ha), key4(loa, hia), pend_a, pa_p, pa_t, pa0, pa1, pa2, pa3, own_a,
+                   oval_a);
+    if (fb && ib < 0)
+      stage_record(part_of(hb), key4(lob, hib), pend_b, pb_p, pb_t, pb0, pb1, pb2, pb3, own_b,
+                   oval_b);
+    serve();
+  };
+
+  auto stripe_pos = [&](uint64_t k) -> int64_t {
+    return P.base_off + (int64_t)(k * STAGE) + (int64_t)wv * kStripe;
+  };
+  auto load_main = [&](uint64_t k) -> uint4 {
+    return load_text16(P.corpus, P.len, stripe_pos(k) + lane * 16);
+  };
+  // lanes 0-3: the 16 bytes after the stripe; lane 4: the 4 bytes before it
+  auto load_side = [&](uint64_t k) -> uint32_t {
+    const int64_t p0 = stripe_pos(k);
+    return lane < 5 ? load_text4(P.corpus, P.len, lane < 4 ? p0 + kStripe + lane * 4 : p0 - 4)
+                    : 0x20202020u;
+  };
+
+  const uint4 blank = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
+  uint4 cur = blank, nx = blank;
+  uint32_t side = 0x20202020u, side_nx = 0x20202020u;
+  if (st0 < st1) {
+    cur = load_main(st0);
+    side = load_side(st0);
+  }
+  if (st0 + 1 < st1) {
+    nx = load_main(st0 + 1);
+    side_nx = load_side(st0 + 1);
+  }
+  uint64_t tokens = 0;  // wave-uniform
 
   for (uint64_t k = st0; k < st1; ++k) {
-    const int64_t ls = stage_pos(k);
-    const int64_t le = ls + STAGE;
-    if (k != st0 && (k - st0) % kSdWin == 0) {
-      __syncthreads();  // every read of the previous window is done
-      sd_base = k;
-      for (uint32_t i = tid; i < kSdWin + 3; i += BLOCK)
-        s_sd[i] = P.stage_doc[min(k + i, n_stages)];
-      __syncthreads();
-    }
-    const uint64_t c0 = s_sd[k - sd_base], c1 = s_sd[k + 1 - sd_base];
-    const uint64_t nb1 = k + 1 < n_stages ? s_sd[k + 2 - sd_base] - c1 : 0;
-    bo0 = bo1;
-    bo1 = bo2;
-    bo2 = doc_start(k + 2);
+    const int64_t p0 = stripe_pos(k);
+    // documents starting in [p0, p0 + kStripeText): the first at or after the stage start is
+    // stage_doc[k]; the bytes after the last stripe of a stage lie in the next stage
+    const uint64_t c0 = P.stage_doc[k];
+    const uint64_t c2 = P.stage_doc[min(k + (wv == NW - 1 ? 2 : 1), n_stages)];
+    const bool plain = c2 == c0 && p0 >= R0 && p0 + (int64_t)kStripeText <= R1;
 
-    // ---- 1. fold + classify; document starts in [ls, le] ---------------------------------
-    // an interior stage (inside [R0, R1), no document start in it or at its end, the next
-    // 16 bytes inside too) needs no range cuts and no boundary bits
-    const uint64_t nbk = c1 - c0;
-    const bool plain = ls >= R0 && le + 16 <= R1 && nbk == 0 && nb1 == 0;
+    // ---- classify; the word bytes just after and before the stripe -----------------------
     uint32_t w16;
     const uint4 g = classify16(cur, &w16);
-    if (!plain) w16 = cut16(w16, ls + tid * 16, R0, R1);
-    s_txt4[tid] = g;
-    s_wm[tid] = (uint16_t)w16;
-    if ((uint64_t)tid < nbk) {
-      const uint64_t rel = bo0 - (uint64_t)ls;
-      atomicOr(&s_bnd[rel >> 5], 1u << (rel & 31));
-    }
-    for (uint64_t j = BLOCK + tid; j < nbk; j += BLOCK) {
-      const uint64_t rel = P.offsets[c0 + j] - (uint64_t)ls;
-      atomicOr(&s_bnd[rel >> 5], 1u << (rel & 31));
-    }
-    if (tid == 0 && plain) {
-      uint32_t nw;
-      s_txt4[BLOCK] = classify16(nx, &nw);
-      s_next_w = nw & 1u;
-      s_next_run = (uint32_t)__builtin_ctz(~nw | 0x10000u);
-    } else if (tid == 0) {
-      // the next stage's first 16 bytes: a word running over the stage end finishes there
-      uint32_t nw;
-      s_txt4[BLOCK] = classify16(nx, &nw);
-      int64_t cut_hi = R1;
-      const bool doc_at_le = nb1 > 0 && (int64_t)bo1 == le;
-      if (nb1 > 0 && (int64_t)bo1 < cut_hi) cut_hi = (int64_t)bo1;
-      nw = cut16(nw, le, R0, cut_hi);
-      if (doc_at_le) {
-        atomicOr(&s_bnd[STAGE >> 5], 1u);
-        nw = 0;
-      }
-      s_next_w = nw & 1u;
-      s_next_run = (uint32_t)__builtin_ctz(~nw | 0x10000u);  // 16: runs past these bytes
-    }
-    // the next stage's text: loaded now, used one stage later
+    if (!plain) w16 = cut16(w16, p0 + lane * 16, R0, R1);
+    ((uint4*)my_txt)[lane] = g;
+    uint32_t sflag;
+    const uint32_t sg = fold_classify4(side, &sflag);
+    if (lane < 4) ((uint32_t*)my_txt)[kStripe / 4 + lane] = sg;
+    const uint32_t m4 = movemask4(sflag);
+    uint32_t nm = (uint32_t)__builtin_amdgcn_readlane((int)m4, 0) |
+                  ((uint32_t)__builtin_amdgcn_readlane((int)m4, 1) << 4) |
+                  ((uint32_t)__builtin_amdgcn_readlane((int)m4, 2) << 8) |
+                  ((uint32_t)__builtin_amdgcn_readlane((int)m4, 3) << 12);
+    uint32_t carry = ((uint32_t)__builtin_amdgcn_readlane((int)m4, 4) >> 3) & 1u;
+    if (p0 - 1 < R0 || p0 - 1 >= R1) carry = 0;
+    if (!plain) nm = cut16(nm, p0 + kStripe, R0, R1);
     cur = nx;
-    nx = blank;
-    if (k + 2 <= st1 && k + 2 < n_stages) nx = load16(k + 2);
-    __syncthreads();
-    // the previous stage's last chunks leave only now, after the load above: stores and loads
-    // retire in one order, so stores issued just before a text wait would be waited for too
-    flush_round();
-
-    // ---- 2. start / last masks, compaction --------------------------------------------
-    const uint32_t prev = tid > 0 ? (s_wm[tid - 1] >> 15) : s_carry[(k & 1) ^ 1];
-    const uint32_t next = tid < BLOCK - 1 ? (s_wm[tid + 1] & 1u) : s_next_w;
-    const uint32_t bnd = plain ? 0u : (s_bnd[tid >> 1] >> ((tid & 1) * 16)) & 0xffffu;
-    const uint32_t bnext = plain ? 0u : (s_bnd[(tid + 1) >> 1] >> (((tid + 1) & 1) * 16)) & 1u;
-    const uint32_t wprev = ((w16 << 1) | prev) & 0xffffu;
-    const uint32_t start16 = w16 & (~wprev | bnd);
-    const uint32_t wnext = (w16 >> 1) | (next << 15);
-    const uint32_t bn16 = (bnd >> 1) | (bnext << 15);
-    const uint32_t last16 = w16 & (~wnext | bn16) & 0xffffu;
-    s_last[tid] = (uint16_t)last16;
-    if (tid == BLOCK - 1) {
-      s_carry[k & 1] = w16 >> 15;
-      s_last[BLOCK] = 0;
+    side = side_nx;
+    if (k + 2 < st1) {
+      nx = load_main(k + 2);
+      side_nx = load_side(k + 2);
     }
-    uint32_t rank0;
-    const uint32_t total = compact_starts<BLOCK>(start16, s_wsum, s_starts, kStartCap, &rank0);
-    tokens += (tid == 0) ? total : 0u;
-    if (!plain)
-      for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
-    const uint32_t next_run = s_next_run;
 
-    // ---- 3. tokens in rounds of BLOCK; staged chunks leave after each round. Document
-    // boundaries can make every byte a start: starts beyond kStartCap take further windows.
-    for (uint32_t w0 = 0; w0 < total; w0 += kStartCap) {
-      if (w0) {
-        __syncthreads();
-        write_starts(start16, rank0, w0, kStartCap, s_starts);
-        __syncthreads();
+    // ---- document starts of the stripe ---------------------------------------------------
+    uint32_t bnd16 = 0, bnext = 0, bnd64 = 0;
+    if (!plain) {
+      if (c2 > c0) {
+        uint64_t j0 = c0, j1 = c2;
+        while (j1 - j0 > 64) {  // first document starting at or after p0
+          const uint64_t m = (j0 + j1) >> 1;
+          if ((int64_t)P.offsets[m] < p0) j0 = m + 1;
+          else j1 = m;
+        }
+        for (uint64_t jb = j0; jb < c2; jb += 64) {
+          const uint64_t j = jb + lane;
+          const int64_t o = j < c2 ? (int64_t)P.offsets[j] : INT64_MAX;
+          if (o >= p0 && o < p0 + (int64_t)kStripeText) {
+            const uint32_t rel = (uint32_t)(o - p0);
+            atomicOr(&my_bnd[rel >> 5], 1u << (rel & 31));
+          }
+          if (__all(o >= p0 + (int64_t)kStripeText)) break;
+        }
+        wave_sync();
       }
-      // one token round per window: each thread takes its tokens back to back. The full-list
-      // the last flush read is emptied for the flush after this round (its carry-overs go
-      // to the other list, which this round fills)
-      if (tid == 0 && flushed > 0) s_nfull[(flushed - 1) & 1] = 0;
-      const uint32_t wend = min(total, w0 + kStartCap);
-      for (uint32_t t = w0 + tid; t < wend; t += BLOCK) token(t - w0, ls, c1, next_run);
-      __syncthreads();
-      ++rounds;
-      if (w0 + kStartCap < total) {  // the stage's last flush waits for the next stage
-        flush_round();
-        __syncthreads();
-      }
+      bnd16 = (my_bnd[lane >> 1] >> ((lane & 1) * 16)) & 0xffffu;
+      bnext = (my_bnd[(lane + 1) >> 1] >> (((lane + 1) & 1) * 16)) & 1u;
+      bnd64 = my_bnd[kStripe / 32] & 0xffffu;
+      wave_sync();
+      if (lane < (int)kBndWords) my_bnd[lane] = 0;
     }
-  }
 
-  // ---- end of range: staged records leave, blocks close; dictionary hits go out ---------
-  __syncthreads();
-  flush_round();
-  __syncthreads();
-  // staging the last overflow records can fill a chunk again: those partitions are listed
-  uint32_t Lc = rounds & 1;
-  while (__syncthreads_or(s_nfull[Lc] > 0)) {
-    if (tid == 0) s_nfull[Lc ^ 1] = 0;
-    __syncthreads();
-    flush_all(Lc, false);
-    __syncthreads();
-    Lc ^= 1;
+    // ---- word starts and ends --------------------------------------------------------------
+    // previous lane's last byte (lane 0: the byte before the stripe); next lane's first byte
+    // (lane 63: the byte after the stripe)
+    const uint32_t prev =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)carry, (int)(w16 >> 15), 0x138, 0xf, 0xf, false);
+    const uint32_t nxt =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(nm & 1u), (int)(w16 & 1u), 0x130, 0xf, 0xf, false);
+    const uint32_t start16 = w16 & (~((w16 << 1) | prev) | bnd16) & 0xffffu;
+    const uint32_t last16 = w16 & (~((w16 >> 1) | (nxt << 15)) | (bnd16 >> 1) | (bnext << 15)) & 0xffffu;
+    // word ends among the 16 bytes after the stripe (the last of them excluded: a word still
+    // running there is longer than 16 bytes), for the word that crosses the stripe end
+    const uint32_t last64 = nm & (~(nm >> 1) | (bnd64 >> 1)) & 0x7fffu;
+    const uint32_t nl =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)last64, (int)last16, 0x130, 0xf, 0xf, false);
+
+    // ---- compaction and tokens, kWaveStarts at a time -------------------------------------
+    const uint32_t c = __popc(start16);
+    const uint32_t incl = wave_incl_scan(c);
+    const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    tokens += n;
+    for (uint32_t w0 = 0; w0 < n; w0 += kWaveStarts) {
+      write_pairs(start16, last16, nl, incl - c, w0, my_pairs);
+      wave_sync();
+      token_round(min(n - w0, kWaveStarts), p0);
+      wave_sync();
+    }
+    if (stalled) break;
   }
-  if (tid < (int)kParts) {
-    // the last (partial) chunk; s_bpos is a multiple of kChunkRec and n < kChunkRec: it fits
-    const uint32_t f = s_fill[tid], head = f >> 16, n = f & 0xffffu;
-    const uint32_t b = s_blk[tid];
-    uint32_t bp = s_bpos[tid];
-    const uint4* src = s_stage + tid * kStageSlots;
+  if (stalled) or32(&hdr->flags, kFlagStall);
+
+  // ---- end of range: the records still held leave, blocks close; dictionary hits go out ---
+  __syncthreads();
+  if (tid < (int)kParts && !(ld_relaxed32(&hdr->flags) & kFlagStall)) {
+    // fewer than kChunkRec records (every full chunk has left); the block has room for them
+    const uint32_t f = s_fill[tid], head = f >> 16;
+    uint32_t n = f & 0xffffu;
+    if (n >= kChunkRec) {  // a full chunk still held: never after a completed scan
+      or32(&hdr->flags, kFlagStall);
+      n = 0;
+    }
+    const uint32_t gb = s_blk[tid], bp = head & (kBlockRec - 1);
     for (uint32_t j = 0; j < n; ++j) {
-      if (b != kNone) {
-        P.arena[((uint64_t)tid * P.R + b) * kBlockRec + bp + j] = src[ring(head, j)];
+      const uint4 r = s_stage[tid * kStageSlots + ((head + j) & kRingMask)];
+      if (gb != kNone) {
+        P.arena[(uint64_t)gb * kBlockRec + bp + j] = r;
       } else {
-        atomicAdd(&s_stat[1], 1u);
-        insert_record(src[ring(head, j)]);
+        ++direct;
+        insert_record(r);
       }
     }
-    if (b != kNone) P.fill[(uint64_t)tid * P.R + b] = (uint16_t)(bp + n);
+    if (gb != kNone) P.fill[gb] = (uint16_t)(bp + n);
   }
   for (uint32_t i = tid; i < nd; i += BLOCK) P.dict_part[(uint64_t)blockIdx.x * D + i] = s_cnt[i];
   if (spilled) atomicAdd(&s_stat[0], spilled);
+  if (direct) atomicAdd(&s_stat[1], direct);
+  if (waits && lane == 0) atomicAdd(&s_stat[2], waits);
+  if (lane == 0 && tokens) add64(&hdr->total_tokens, tokens);
   __syncthreads();
   if (tid == 0) {
     if (s_stat[0]) add64(&hdr->stat[0], s_stat[0]);
-    add64(&hdr->total_tokens, tokens);
     if (s_stat[1]) add64(&hdr->stat[1], s_stat[1]);
     if (s_stat[2]) add64(&hdr->stat[3], s_stat[2]);
   }

@@ -32,10 +32,9 @@ struct CountParams {
 
 // two-pass global count (wc_global.hip)
 constexpr uint32_t kParts = 256;         // partitions of the spilled records
-constexpr uint32_t kStageSlots = 12;     // records staged per partition in LDS
+constexpr uint32_t kStageSlots = 16;     // records staged per partition in LDS (a ring)
 constexpr uint32_t kChunkRec = 8;        // records per write to the arena (128 bytes)
 constexpr uint32_t kBlockRec = 256;      // records per arena block (4 KiB)
-constexpr uint32_t kOverflow = 128;      // records of one token round that found their ring full
 constexpr uint32_t kDictMax = 2560;      // hot-word dictionary capacity (words)
 constexpr uint32_t kMapBlock = 1024;     // pass-1 workgroup
 constexpr uint32_t kGlobalStage = kMapBlock * 16;  // bytes scanned per pass-1 stage
@@ -43,7 +42,9 @@ constexpr uint32_t kDictBuckets = 640;   // dictionary buckets of 8 slots
 constexpr uint32_t kSampleStages = 512;  // pass-1 stages sampled (first 8 KiB of each)
 constexpr uint32_t kSampleLds = 2048;    // LDS table of one sampled stage
 constexpr uint64_t kSampleSlots = 1ull << 19;  // device table of the sample
-constexpr uint32_t kSdWin = 64;          // stage-to-document entries cached in LDS
+constexpr uint32_t kStripe = 1024;       // pass-1 bytes per wave per stage
+constexpr uint32_t kStripeText = kStripe + 16;  // staged per wave: the stripe and 16 bytes after
+constexpr uint32_t kWaveStarts = 128;    // (start, end) pairs of one wave listed at a time
 constexpr uint32_t kDictCols = 64;       // dictionary words totalled per pass-2 workgroup
 constexpr uint32_t kWinBlocks = 2048;    // pass 2 lists the non-empty blocks this many at a time
 constexpr uint32_t kRedSlots = 8192;     // pass-2 LDS slots (13-bit entry indices)
@@ -83,7 +84,7 @@ struct GlobalParams {
   uint32_t* dict_part;       // [map_grid][dict_cap] dictionary hits per pass-1 workgroup
   Slot* sample_table;        // [kSampleSlots]
   Header* sample_hdr;
-  uint32_t R;                // arena blocks per partition
+  uint32_t R;                // arena blocks per partition (kParts * R < 2^32)
   uint32_t reduce_entries;   // pass-2 LDS entries (distinct words of a partition, <= kRedSlots)
   uint32_t reduce_cap;       // entries used before further new words go to the global table
   uint32_t S;                // static blocks per partition: block j * map_grid + w is the

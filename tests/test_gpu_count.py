@@ -190,7 +190,7 @@ def test_words_across_stage_boundaries(stage, path):
         pos += L + len(sep)
     text = b"".join(parts)
     if path == "spill" and stage != 8192:
-        pytest.skip("the two-pass kernel scans 8 KiB stages")
+        pytest.skip("the two-pass kernel has one stage size (16 KiB, 1 KiB per wave)")
     for shift in (0, 1, 7, 15):
         t = b"q" * shift + text
         tu = wc.make_tuning(stage_bytes=stage)
