@@ -36,11 +36,16 @@ WC_DEV uint32_t word_hash32(uint64_t lo, uint64_t hi) {
 
 WC_DEV uint32_t part_of(uint32_t h) { return h & (kParts - 1); }
 
-// The 32-bit word hash h serves three independent uses: partition = bits 0-7, dictionary tag
-// = bits 8-14 (with bit 7 of the tag byte set, so a tag is never 0), dictionary bucket = the
-// high bits (the high half of h * buckets).
-WC_DEV uint32_t dict_tag(uint32_t h) { return ((h >> 8) & 0x7fu) | 0x80u; }
-WC_DEV uint32_t dict_bucket(uint32_t h, uint32_t nb) { return __umulhi(h, nb); }
+// The 32-bit word hash h serves the partition (bits 0-7) and the dictionary: group g = bits 0-8;
+// the group's slots lie in region g mod 16 (256 slots); a word's slot in the region is an 8-bit
+// field of h (bits 9-16, or bits 17-24 when bit 8 of the group's displacement is set) XOR the
+// displacement's low 8 bits.
+WC_DEV uint32_t dict_group(uint32_t h) { return h & (kDispBuckets - 1); }
+WC_DEV uint32_t dict_field(uint32_t h, uint32_t sel) { return (h >> (9 + 8 * sel)) & 0xffu; }
+WC_DEV uint32_t dict_slot(uint32_t h, uint32_t d) {
+  const uint32_t g = dict_group(h);
+  return ((g & (kDictRegions - 1)) << 8) | ((dict_field(h, (d >> 8) & 1u) ^ d) & 0xffu);
+}
 
 WC_DEV uint4 key4(uint64_t lo, uint64_t hi) {
   return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
@@ -51,27 +56,14 @@ WC_DEV uint64_t short_key_g(uint64_t lo, uint64_t hi, uint64_t key_mask) {
   return finish_key(fnv_packed(lo, hi, packed_len(lo, hi)), key_mask);
 }
 
-// Index of the word in the dictionary, or -1: one 8-byte read of the bucket's tags and, at the
-// same time, one 16-byte read of its 8 key indices; a SWAR match of the tag against all 8 (a
-// flagged byte above a true match may be spurious; the key compare settles every candidate),
-// and a key read per candidate.
-WC_DEV int dict_find(const uint64_t* tags8, const uint16_t* idx, const uint4* keys, uint32_t nb,
-                     uint64_t lo, uint64_t hi, uint32_t h) {
-  const uint32_t b = dict_bucket(h, nb);
-  const uint64_t t8 = tags8[b];
-  const uint4 row = ((const uint4*)idx)[b];
-  const uint64_t x = t8 ^ (0x0101010101010101ull * dict_tag(h));
-  uint64_t z = (x - 0x0101010101010101ull) & ~x & 0x8080808080808080ull;
+// Index of the word in the dictionary, or -1: the displacement of its group, the key index in
+// its slot, one key compare (an empty slot points at the all-zero key).
+WC_DEV int dict_find(const uint16_t* disp, const uint16_t* slots, const uint4* keys, uint64_t lo,
+                     uint64_t hi, uint32_t h) {
+  const uint32_t i = slots[dict_slot(h, disp[dict_group(h)])];
+  const uint4 k = keys[i];
   const uint4 want = key4(lo, hi);
-  while (z) {
-    const uint32_t j = (uint32_t)(__ffsll((unsigned long long)z) - 1) >> 3;
-    const uint32_t d = j < 4 ? (j < 2 ? row.x : row.y) : (j < 6 ? row.z : row.w);
-    const uint32_t i = (j & 1) ? d >> 16 : d & 0xffffu;
-    const uint4 k = keys[i];
-    if (k.x == want.x && k.y == want.y && k.z == want.z && k.w == want.w) return (int)i;
-    z &= z - 1;
-  }
-  return -1;
+  return (k.x == want.x && k.y == want.y && k.z == want.z && k.w == want.w) ? (int)i : -1;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -262,6 +254,14 @@ WC_DEV uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
+// Orders this wave's LDS accesses around the point in the compiler (the hardware keeps one
+// wave's LDS operations in order).
+WC_DEV void wave_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Positions (tid * 16 + bit) of the starts in mask m whose ranks, counted from `rank`, fall
 // in [w0, w0 + cap), stored at s_starts[rank - w0].
 WC_DEV void write_starts(uint32_t m, uint32_t rank, uint32_t w0, uint32_t cap,
@@ -440,62 +440,167 @@ __global__ void dict_select_kernel(GlobalParams P) {
   }
 }
 
-// One workgroup: place the selected words into their buckets, hottest first (a counting sort
-// on the sample counts). A word whose bucket is full is left out, so only the coldest words
-// can be left out.
+// One workgroup builds the perfect hash of the selected words (hash and displace, after
+// Belazzougui, Botelho and Dietzfelbinger): words are grouped by the low 9 bits of their hash;
+// each of 16 waves fills one region of 256 slots with its 32 groups, largest first, and a group
+// takes the first displacement that sends all of its words to free slots. Inside a group the
+// hottest words come first; a word that cannot be placed with the others (the same slot field
+// as a hotter word of its group in both fields, or no free displacement) is left out of the
+// dictionary, which only moves its counting to the partitions.
 __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
-  __shared__ uint32_t s_fill[kDictBuckets];
-  __shared__ uint32_t s_pos[256];
-  __shared__ uint16_t s_order[kDictMax];
-  __shared__ uint32_t s_n;
+  constexpr uint32_t kMaxGroup = 64;  // words of one group placed at most (one per lane)
+  constexpr uint32_t kRegionGroups = kDispBuckets / kDictRegions;
+  static_assert(kDictSlots == kDictRegions * 256 && kRegionGroups <= 64, "256-slot regions");
+  __shared__ uint32_t s_h[kDictMax];
+  __shared__ uint16_t s_gkeys[kDictMax];  // key indices grouped by group, hottest first
+  __shared__ uint32_t s_gn[kDispBuckets], s_gstart[kDispBuckets];
+  __shared__ uint8_t s_ord[kDictRegions][kRegionGroups];
+  __shared__ uint32_t s_occ[kDictSlots / 32];
+  __shared__ uint16_t s_slot[kDictSlots];
+  __shared__ uint16_t s_disp[kDispBuckets];
+  __shared__ uint32_t s_n, s_placed;
   const uint32_t tid = threadIdx.x;
   if (tid == 0) {
     uint32_t t, acc, room;
     dict_threshold(P.dict->hist, P.dict_cap, &t, &acc, &room);
-    uint32_t low = P.dict->n_low;
+    const uint32_t low = P.dict->n_low;
     s_n = acc + (low < room ? low : room);
+    s_placed = 0;
   }
-  for (uint32_t i = tid; i < kDictBuckets; i += blockDim.x) s_fill[i] = 0;
-  for (uint32_t i = tid; i < 256; i += blockDim.x) s_pos[i] = 0;
+  for (uint32_t i = tid; i < kDispBuckets; i += blockDim.x) {
+    s_gn[i] = 0;
+    s_disp[i] = 0;
+  }
+  for (uint32_t i = tid; i < kDictSlots / 32; i += blockDim.x) s_occ[i] = 0;
   __syncthreads();
   const uint32_t n = s_n;
-  for (uint32_t i = tid; i < n; i += blockDim.x) atomicAdd(&s_pos[P.dict->cnt[i]], 1u);
-  __syncthreads();
-  if (tid == 0) {  // start of each count class, hottest class first
-    uint32_t a = 0;
-    for (int c = 255; c >= 0; --c) {
-      uint32_t v = s_pos[c];
-      s_pos[c] = a;
-      a += v;
-    }
+  for (uint32_t i = tid; i < kDictSlots; i += blockDim.x) s_slot[i] = (uint16_t)n;
+  for (uint32_t i = tid; i < n; i += blockDim.x) {
+    const uint4 k = P.dict->keys[i];
+    const uint32_t h = word_hash32((uint64_t)k.x | ((uint64_t)k.y << 32),
+                                   (uint64_t)k.z | ((uint64_t)k.w << 32));
+    s_h[i] = h;
+    atomicAdd(&s_gn[dict_group(h)], 1u);
   }
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += blockDim.x)
-    s_order[atomicAdd(&s_pos[P.dict->cnt[i]], 1u)] = (uint16_t)i;
+  if (tid < 64) {  // group starts: a scan over the groups, 8 per lane
+    uint32_t v[kDispBuckets / 64], sum = 0;
+    for (uint32_t j = 0; j < kDispBuckets / 64; ++j) {
+      v[j] = sum;
+      sum += s_gn[tid * (kDispBuckets / 64) + j];
+    }
+    const uint32_t incl = wave_incl_scan(sum);
+    for (uint32_t j = 0; j < kDispBuckets / 64; ++j)
+      s_gstart[tid * (kDispBuckets / 64) + j] = incl - sum + v[j];
+  }
   __syncthreads();
-  uint32_t nb = (P.dict_cap + 3) / 4;  // half-full buckets
-  nb = nb < 16 ? 16 : (nb > kDictBuckets ? kDictBuckets : nb);
-  uint8_t* tag_bytes = (uint8_t*)P.dict->tags;
-  for (uint32_t r0 = 0; r0 < n; r0 += blockDim.x) {
-    const uint32_t r = r0 + tid;
-    if (r < n) {
-      const uint32_t i = s_order[r];
-      const uint4 k = P.dict->keys[i];
-      const uint64_t lo = (uint64_t)k.x | ((uint64_t)k.y << 32), hi = (uint64_t)k.z | ((uint64_t)k.w << 32);
-      const uint32_t h = word_hash32(lo, hi);
-      const uint32_t b = dict_bucket(h, nb);
-      const uint32_t slot = atomicAdd(&s_fill[b], 1u);
-      if (slot < 8) {
-        tag_bytes[b * 8 + slot] = (uint8_t)dict_tag(h);
-        P.dict->idx[b * 8 + slot] = (uint16_t)i;
+  for (uint32_t g = tid; g < kDispBuckets; g += blockDim.x) s_gn[g] = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += blockDim.x) {
+    const uint32_t g = dict_group(s_h[i]);
+    s_gkeys[s_gstart[g] + atomicAdd(&s_gn[g], 1u)] = (uint16_t)i;
+  }
+  __syncthreads();
+  for (uint32_t g = tid; g < kDispBuckets; g += blockDim.x) {  // hottest first in each group
+    uint16_t* a = s_gkeys + s_gstart[g];
+    const uint32_t m = s_gn[g];
+    for (uint32_t x = 1; x < m; ++x) {
+      const uint16_t v = a[x];
+      const uint32_t cv = P.dict->cnt[v];
+      uint32_t y = x;
+      while (y > 0 && P.dict->cnt[a[y - 1]] < cv) {
+        a[y] = a[y - 1];
+        --y;
       }
+      a[y] = v;
     }
-    __syncthreads();  // the next (colder) round sees these placements
   }
+  __syncthreads();
+  const uint32_t lane = tid & 63, r = tid >> 6;  // wave r fills region r
+  if (r < kDictRegions) {
+    // the region's groups g = r + 16 L, largest first
+    const uint32_t my_n = lane < kRegionGroups ? s_gn[r + kDictRegions * lane] : 0u;
+    uint32_t rank = 0;
+    for (uint32_t x = 0; x < kRegionGroups; ++x) {
+      const uint32_t nx = (uint32_t)__builtin_amdgcn_readlane((int)my_n, (int)x);
+      rank += (nx > my_n || (nx == my_n && x < lane)) ? 1u : 0u;
+    }
+    if (lane < kRegionGroups) s_ord[r][rank] = (uint8_t)lane;
+    wave_sync();
+    uint32_t placed = 0;
+    for (uint32_t o = 0; o < kRegionGroups; ++o) {
+      const uint32_t g = r + kDictRegions * s_ord[r][o];
+      const uint32_t m = min(s_gn[g], kMaxGroup);
+      if (m == 0) break;  // the rest are empty
+      const uint32_t ki = lane < m ? s_gkeys[s_gstart[g] + lane] : 0u;
+      const uint32_t h = s_h[ki];
+      // field select: the one that leaves fewer words out (a word whose field repeats a hotter
+      // word's field is left out)
+      const uint32_t f0 = dict_field(h, 0), f1 = dict_field(h, 1);
+      bool k0 = lane < m, k1 = lane < m;
+      for (uint32_t x = 0; x < m; ++x) {
+        const uint32_t a0 = (uint32_t)__builtin_amdgcn_readlane((int)f0, (int)x);
+        const uint32_t a1 = (uint32_t)__builtin_amdgcn_readlane((int)f1, (int)x);
+        if (x < lane && a0 == f0) k0 = false;
+        if (x < lane && a1 == f1) k1 = false;
+      }
+      const uint64_t km0 = __ballot(k0), km1 = __ballot(k1);
+      const uint32_t sel = __popcll(km1) > __popcll(km0) ? 1u : 0u;
+      uint64_t km = sel ? km1 : km0;
+      const uint32_t f = sel ? f1 : f0;
+      uint32_t d = 0;
+      bool found = false;
+      while (km && !found) {
+        for (uint32_t base = 0; base < 256 && !found; base += 64) {
+          const uint32_t cand = base + lane;
+          bool ok = true;
+          for (uint64_t rem = km; rem;) {
+            uint32_t sl[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              sl[u] = 0xffffffffu;
+              if (rem) {
+                const uint32_t x = (uint32_t)__ffsll((unsigned long long)rem) - 1;
+                rem &= rem - 1;
+                sl[u] = (r << 8) | (((uint32_t)__builtin_amdgcn_readlane((int)f, (int)x) ^ cand) & 0xffu);
+              }
+            }
+            uint32_t wv8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) wv8[u] = sl[u] != 0xffffffffu ? s_occ[sl[u] >> 5] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (sl[u] != 0xffffffffu && ((wv8[u] >> (sl[u] & 31)) & 1u)) ok = false;
+          }
+          const uint64_t okm = __ballot(ok);
+          if (okm) {
+            d = base + (uint32_t)__ffsll((unsigned long long)okm) - 1;
+            found = true;
+          }
+        }
+        if (!found) km &= ~(1ull << (63 - __clzll(km)));  // leave out the coldest and retry
+      }
+      if (found) {
+        if ((km >> lane) & 1ull) {
+          const uint32_t sl = (r << 8) | ((f ^ d) & 0xffu);
+          atomicOr(&s_occ[sl >> 5], 1u << (sl & 31));
+          s_slot[sl] = (uint16_t)ki;
+        }
+        if (lane == 0) s_disp[g] = (uint16_t)(d | (sel << 8));
+        placed += (uint32_t)__popcll(km);
+      }
+      wave_sync();
+    }
+    if (lane == 0) atomicAdd(&s_placed, placed);
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < kDispBuckets; i += blockDim.x) P.dict->disp[i] = s_disp[i];
+  for (uint32_t i = tid; i < kDictSlots; i += blockDim.x) P.dict->slot[i] = s_slot[i];
   if (tid == 0) {
+    P.dict->keys[n] = make_uint4(0, 0, 0, 0);
     P.dict->n = n;
-    P.dict->nb = nb;
-    P.hdr->stat[2] = n;
+    P.dict->placed = s_placed;
+    P.hdr->stat[2] = s_placed;
   }
 }
 
@@ -509,7 +614,7 @@ constexpr uint32_t kSpinLimit = 1u << 24;                // rounds of one wait b
 
 size_t global_map_dyn(uint32_t dict_cap) {
   return (size_t)kParts * kStageSlots * 16 + (size_t)kMapWaves * kStripeText +
-         (size_t)kDictBuckets * (8 + 16) + (size_t)dict_cap * 20 +
+         (size_t)(kDispBuckets + kDictSlots) * 2 + (size_t)(dict_cap + 1) * 16 + (size_t)dict_cap * 4 +
          (size_t)kMapWaves * kWaveStarts * 4;
 }
 
@@ -543,14 +648,6 @@ WC_DEV void write_pairs(uint32_t m, uint32_t last16, uint32_t nl, uint32_t rank,
     ++rank;
     m &= m - 1;
   }
-}
-
-// Orders this wave's LDS accesses around the point in the compiler (the hardware keeps one
-// wave's LDS operations in order).
-WC_DEV void wave_sync() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_wave_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // One workgroup of BLOCK threads scans a contiguous range of STAGE-byte stages; wave v takes
@@ -594,10 +691,10 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   const uint32_t D = P.dict_cap;
   uint4* s_stage = (uint4*)s_dyn;                               // [kParts][kStageSlots]
   uint8_t* s_txt = (uint8_t*)(s_stage + kParts * kStageSlots);  // [NW][kStripeText]
-  uint64_t* s_tags8 = (uint64_t*)(s_txt + NW * kStripeText);    // [kDictBuckets]
-  uint16_t* s_idx = (uint16_t*)(s_tags8 + kDictBuckets);        // [kDictBuckets * 8]
-  uint4* s_keys = (uint4*)(s_idx + kDictBuckets * 8);           // [D]
-  uint32_t* s_cnt = (uint32_t*)(s_keys + D);                    // [D]
+  uint16_t* s_disp = (uint16_t*)(s_txt + NW * kStripeText);    // [kDispBuckets]
+  uint16_t* s_dslot = s_disp + kDispBuckets;                    // [kDictSlots]
+  uint4* s_keys = (uint4*)(s_dslot + kDictSlots);               // [D + 1]
+  uint32_t* s_cnt = (uint32_t*)(s_keys + D + 1);                // [D]
   uint32_t* s_pairs = s_cnt + D;                                // [NW][kWaveStarts]
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -609,13 +706,11 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   const uint64_t n_stages = P.n_stages;
   const int64_t R0 = (int64_t)P.offsets[0], R1 = (int64_t)P.offsets[P.n_docs];
 
-  const uint32_t nd = P.dict->n, nb = P.dict->nb;
-  for (uint32_t i = tid; i < nb; i += BLOCK) s_tags8[i] = P.dict->tags[i];
-  for (uint32_t i = tid; i < nb * 8; i += BLOCK) s_idx[i] = P.dict->idx[i];
-  for (uint32_t i = tid; i < nd; i += BLOCK) {
-    s_keys[i] = P.dict->keys[i];
-    s_cnt[i] = 0;
-  }
+  const uint32_t nd = P.dict->n;
+  for (uint32_t i = tid; i < kDispBuckets; i += BLOCK) s_disp[i] = P.dict->disp[i];
+  for (uint32_t i = tid; i < kDictSlots; i += BLOCK) s_dslot[i] = P.dict->slot[i];
+  for (uint32_t i = tid; i <= nd; i += BLOCK) s_keys[i] = P.dict->keys[i];
+  for (uint32_t i = tid; i < nd; i += BLOCK) s_cnt[i] = 0;
   for (uint32_t i = tid; i < kParts * kStageSlots; i += BLOCK) s_stage[i] = make_uint4(0, 0, 0, 0);
   // This workgroup's j-th own block of a partition is j * G + w; past its S / G own blocks it
   // takes blocks from [S, R) with an atomic. A block is filled completely before the next, so
@@ -796,8 +891,8 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     if (fa) pack_word(my_txt, sa, ea - sa + 1, &loa, &hia);
     if (fb) pack_word(my_txt, sb, eb - sb + 1, &lob, &hib);
     const uint32_t ha = word_hash32(loa, hia), hb = word_hash32(lob, hib);
-    const int ia = fa && nd ? dict_find(s_tags8, s_idx, s_keys, nb, loa, hia, ha) : -1;
-    const int ib = fb && nd ? dict_find(s_tags8, s_idx, s_keys, nb, lob, hib, hb) : -1;
+    const int ia = fa ? dict_find(s_disp, s_dslot, s_keys, loa, hia, ha) : -1;
+    const int ib = fb ? dict_find(s_disp, s_dslot, s_keys, lob, hib, hb) : -1;
     if (ia >= 0) atomicAdd(&s_cnt[ia], 1u);
     if (ib >= 0) atomicAdd(&s_cnt[ib], 1u);
     if (fa && ia < 0)

@@ -38,7 +38,9 @@ constexpr uint32_t kBlockRec = 256;      // records per arena block (4 KiB)
 constexpr uint32_t kDictMax = 2560;      // hot-word dictionary capacity (words)
 constexpr uint32_t kMapBlock = 1024;     // pass-1 workgroup
 constexpr uint32_t kGlobalStage = kMapBlock * 16;  // bytes scanned per pass-1 stage
-constexpr uint32_t kDictBuckets = 640;   // dictionary buckets of 8 slots
+constexpr uint32_t kDispBuckets = 512;   // dictionary: displacement buckets (low 9 hash bits)
+constexpr uint32_t kDictSlots = 4096;    // dictionary: slots of the perfect hash
+constexpr uint32_t kDictRegions = 16;    // dictionary: regions of 256 slots (group mod 16)
 constexpr uint32_t kSampleStages = 512;  // pass-1 stages sampled (first 8 KiB of each)
 constexpr uint32_t kSampleLds = 2048;    // LDS table of one sampled stage
 constexpr uint64_t kSampleSlots = 1ull << 19;  // device table of the sample
@@ -49,19 +51,20 @@ constexpr uint32_t kDictCols = 64;       // dictionary words totalled per pass-2
 constexpr uint32_t kWinBlocks = 2048;    // pass 2 lists the non-empty blocks this many at a time
 constexpr uint32_t kRedSlots = 8192;     // pass-2 LDS slots (13-bit entry indices)
 
-// Dictionary of hot words, chosen from a sample and read-only while the text is scanned.
-// A word sits in one 8-slot bucket; a bucket is 8 one-byte tags (0 = empty) in one 64-bit
-// word, and each slot has the 16-bit index of its key.
+// Dictionary of hot words, chosen from a sample and read-only while the text is scanned: a
+// perfect hash by hash-and-displace. A word with hash h belongs to group h mod 512; the group's
+// displacement picks its slot in region (h mod 16) (see dict_slot); the slot holds its key
+// index; empty slots hold n, the index of an all-zero key that no word matches.
 struct DictImage {
   uint32_t n;            // words (key entries) in the dictionary
-  uint32_t nb;           // buckets in use
+  uint32_t placed;       // words placed in the perfect hash (the others are never looked up)
   uint32_t n_high;       // selection: words above the count threshold
   uint32_t n_low;        // selection: words at the threshold competing for the rest
   uint32_t hist[256];    // sample counts (clamped at 255) -> number of words
-  uint64_t tags[kDictBuckets];         // 8 tags per bucket
-  uint16_t idx[kDictBuckets * 8];      // key index of each slot
-  uint4 keys[kDictMax];  // packed words (lo, hi)
-  uint32_t cnt[kDictMax];  // their sample counts (clamped at 255), for hottest-first placement
+  uint16_t disp[kDispBuckets];
+  uint16_t slot[kDictSlots];
+  uint4 keys[kDictMax + 1];  // packed words (lo, hi); keys[n] = 0
+  uint32_t cnt[kDictMax];    // their sample counts (clamped at 255)
 };
 
 struct GlobalParams {
