@@ -220,7 +220,8 @@ WC_DEV uint32_t cut16(uint32_t w16, int64_t p, int64_t a, int64_t b) {
   return w16 & m;
 }
 
-// Packed bytes of the word at byte s of the staged text (wl <= 16 bytes, all staged).
+// Packed bytes of the word at byte s of the staged text (1 <= wl <= 16 bytes, all staged):
+// five dword reads, byte alignment, and the bytes past the word cleared.
 WC_DEV void pack_word(const uint8_t* s_txt, uint32_t s, uint32_t wl, uint64_t* lo, uint64_t* hi) {
   const uint32_t* tw = (const uint32_t*)s_txt;
   const uint32_t di = s >> 2, sh = s & 3;
@@ -229,14 +230,10 @@ WC_DEV void pack_word(const uint8_t* s_txt, uint32_t s, uint32_t wl, uint64_t* l
                ((uint64_t)__builtin_amdgcn_alignbyte(d2, d1, sh) << 32);
   uint64_t b = (uint64_t)__builtin_amdgcn_alignbyte(d3, d2, sh) |
                ((uint64_t)__builtin_amdgcn_alignbyte(d4, d3, sh) << 32);
-  if (wl < 8) {
-    a &= (1ull << (8 * wl)) - 1;
-    b = 0;
-  } else if (wl == 8) {
-    b = 0;
-  } else if (wl < 16) {
-    b &= (1ull << (8 * (wl - 8))) - 1;
-  }
+  const uint32_t ka = wl < 8 ? 64 - 8 * wl : 0u;    // bits of a past the word
+  const uint32_t kb = wl < 16 ? 128 - 8 * wl : 0u;  // bits of b past the word (>= 64: all)
+  a = (a << ka) >> ka;
+  b = kb >= 64 ? 0ull : (b << kb) >> kb;
   *lo = a;
   *hi = b;
 }
@@ -754,16 +751,12 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
 
   uint32_t spilled = 0, direct = 0, waits = 0;
   bool stalled = false;
-  // Per lane and token slot (a: tokens t < 64 of a round, b: t >= 64): a record waiting for a
-  // slot (pend: partition, ticket, record) and a chunk this lane owns ((partition << 16) | last
-  // ticket). Chunks are sent out in the same round.
-  bool pend_a = false, pend_b = false, own_a = false, own_b = false;
-  uint32_t pa_p = 0, pa_t = 0, pb_p = 0, pb_t = 0, oval_a = 0, oval_b = 0;
-  uint32_t pa0 = 0, pa1 = 0, pa2 = 0, pa3 = 0, pb0 = 0, pb1 = 0, pb2 = 0, pb3 = 0;
 
-  // One pass over up to 8 owned chunks (a-slot owners first, then b-slot owners), 8 lanes (one
-  // record each) per chunk. Owned chunks that are not ready stay owned.
-  auto flush_pass = [&](uint64_t oma, uint64_t omb) {
+  // One pass over up to 8 owned chunks (owners of slot a first, then of slot b), 8 lanes (one
+  // record each) per chunk; oval = (partition << 16) | last ticket. Chunks that are not ready
+  // stay owned.
+  auto flush_pass = [&](bool& own_a, bool& own_b, uint32_t oval_a, uint32_t oval_b) {
+    const uint64_t oma = __ballot(own_a), omb = __ballot(own_b);
     const uint32_t na = (uint32_t)__popcll(oma);
     const uint32_t ia = __builtin_amdgcn_mbcnt_hi((uint32_t)(oma >> 32),
                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)oma, 0u));
@@ -811,56 +804,6 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     if (own_b && ib < 8 && ((okm >> (8 * ib)) & 0xffull) == 0xffull) own_b = false;
     wave_sync();  // s_dq is rewritten by the next pass
   };
-  auto try_place = [&](bool& pend, uint32_t p, uint32_t tick, const uint4 rec) {
-    const uint32_t head =
-        __hip_atomic_load(&s_fill[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 16;
-    if (((tick - head) & 0xffffu) < kStageSlots) {
-      s_stage[p * kStageSlots + (tick & kRingMask)] = rec;
-      pend = false;
-    }
-  };
-  // Wave-uniform: places waiting records and sends out owned chunks until none is left.
-  auto serve = [&]() {
-    uint32_t spins = 0;
-    while (!stalled) {
-      if (pend_a) try_place(pend_a, pa_p, pa_t, make_uint4(pa0, pa1, pa2, pa3));
-      if (pend_b) try_place(pend_b, pb_p, pb_t, make_uint4(pb0, pb1, pb2, pb3));
-      // a chunk can leave only once the owner's own record is in it
-      const uint64_t oma = __ballot(own_a && !pend_a), omb = __ballot(own_b && !pend_b);
-      if (!__any(pend_a || pend_b || own_a || own_b)) break;
-      if (spins) __builtin_amdgcn_s_sleep(1);  // waiting on other waves
-      if (++spins >= kSpinLimit) {
-        stalled = true;
-        break;
-      }
-      if (oma | omb) flush_pass(oma, omb);
-    }
-    waits += spins > 1 ? spins - 1 : 0;
-  };
-  // a token that missed the dictionary: reserve its ticket, write the record if its slot is
-  // free, own the chunk it completes
-  auto stage_record = [&](uint32_t p, const uint4 rec, bool& pend, uint32_t& pp, uint32_t& pt,
-                          uint32_t& r0, uint32_t& r1, uint32_t& r2, uint32_t& r3, bool& own,
-                          uint32_t& oval) {
-    const uint32_t old = atomicAdd(&s_fill[p], 1u);
-    const uint32_t tick = ((old >> 16) + old) & 0xffffu;
-    if ((old & 0xffffu) < kStageSlots) {
-      s_stage[p * kStageSlots + (tick & kRingMask)] = rec;
-    } else {
-      pend = true;
-      pp = p;
-      pt = tick;
-      r0 = rec.x;
-      r1 = rec.y;
-      r2 = rec.z;
-      r3 = rec.w;
-    }
-    if ((tick & (kChunkRec - 1)) == kChunkRec - 1) {
-      own = true;
-      oval = (p << 16) | tick;
-    }
-    ++spilled;
-  };
   // a word longer than 16 bytes (or with its end beyond the staged bytes): from device memory,
   // into the global table
   auto long_token = [&](int64_t p0, uint32_t s, uint32_t e) {
@@ -877,7 +820,9 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     }
   };
 
-  // One round: pairs t and t + 64 of this wave's list (t = lane), for those below nw.
+  // One round: pairs t and t + 64 of this wave's list (t = lane), for those below nw. A token
+  // that misses the dictionary reserves a ticket and writes its record if the slot is free;
+  // then the wave places the records that waited and sends out the chunks its lanes own.
   auto token_round = [&](uint32_t nw, int64_t p0) {
     const uint32_t ta = lane, tb = lane + 64;
     const uint32_t pra = ta < nw ? my_pairs[ta] : 0u, prb = tb < nw ? my_pairs[tb] : 0u;
@@ -895,13 +840,51 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     const int ib = fb ? dict_find(s_disp, s_dslot, s_keys, lob, hib, hb) : -1;
     if (ia >= 0) atomicAdd(&s_cnt[ia], 1u);
     if (ib >= 0) atomicAdd(&s_cnt[ib], 1u);
-    if (fa && ia < 0)
-      stage_record(part_of(ha), key4(loa, hia), pend_a, pa_p, pa_t, pa0, pa1, pa2, pa3, own_a,
-                   oval_a);
-    if (fb && ib < 0)
-      stage_record(part_of(hb), key4(lob, hib), pend_b, pb_p, pb_t, pb0, pb1, pb2, pb3, own_b,
-                   oval_b);
-    serve();
+    const bool ma = fa && ia < 0, mb = fb && ib < 0;
+    const uint32_t pa = part_of(ha), pb = part_of(hb);
+    uint32_t oa = 0, ob = 0;
+    if (ma) oa = atomicAdd(&s_fill[pa], 1u);
+    if (mb) ob = atomicAdd(&s_fill[pb], 1u);
+    const uint32_t tka = ((oa >> 16) + oa) & 0xffffu, tkb = ((ob >> 16) + ob) & 0xffffu;
+    const uint4 reca = key4(loa, hia), recb = key4(lob, hib);
+    bool pend_a = ma && (oa & 0xffffu) >= kStageSlots, pend_b = mb && (ob & 0xffffu) >= kStageSlots;
+    if (ma && !pend_a) s_stage[pa * kStageSlots + (tka & kRingMask)] = reca;
+    if (mb && !pend_b) s_stage[pb * kStageSlots + (tkb & kRingMask)] = recb;
+    bool own_a = ma && (tka & (kChunkRec - 1)) == kChunkRec - 1;
+    bool own_b = mb && (tkb & (kChunkRec - 1)) == kChunkRec - 1;
+    spilled += (ma ? 1u : 0u) + (mb ? 1u : 0u);
+    uint32_t spins = 0;
+    while (__any(pend_a || pend_b || own_a || own_b)) {
+      if (spins) __builtin_amdgcn_s_sleep(1);  // waiting on other waves
+      if (++spins >= kSpinLimit || stalled) {
+        stalled = true;
+        break;
+      }
+      if (pend_a) {
+        const uint32_t head =
+            __hip_atomic_load(&s_fill[pa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 16;
+        if (((tka - head) & 0xffffu) < kStageSlots) {
+          s_stage[pa * kStageSlots + (tka & kRingMask)] = reca;
+          pend_a = false;
+        }
+      }
+      if (pend_b) {
+        const uint32_t head =
+            __hip_atomic_load(&s_fill[pb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 16;
+        if (((tkb - head) & 0xffffu) < kStageSlots) {
+          s_stage[pb * kStageSlots + (tkb & kRingMask)] = recb;
+          pend_b = false;
+        }
+      }
+      // a chunk can leave only once the owner's own record is in it
+      bool fa2 = own_a && !pend_a, fb2 = own_b && !pend_b;
+      if (__any(fa2 || fb2)) {
+        flush_pass(fa2, fb2, (pa << 16) | tka, (pb << 16) | tkb);
+        own_a = own_a && (pend_a || fa2);
+        own_b = own_b && (pend_b || fb2);
+      }
+    }
+    waits += spins > 1 ? spins - 1 : 0;
   };
 
   auto stripe_pos = [&](uint64_t k) -> int64_t {
