@@ -25,12 +25,16 @@
 
 namespace wc {
 
+// 32-bit hash of a packed word (16 bytes as four dwords): the dwords folded with rotations,
+// then the 32-bit finaliser of MurmurHash3 (Appleby) for avalanche; two multiplies.
 WC_DEV uint32_t word_hash32(uint64_t lo, uint64_t hi) {
-  uint32_t a = (uint32_t)lo, b = (uint32_t)(lo >> 32), c = (uint32_t)hi, d = (uint32_t)(hi >> 32);
-  uint32_t h = a * 0x9E3779B1u ^ (b * 0x85EBCA77u) ^ (c * 0xC2B2AE3Du) ^ (d * 0x27D4EB2Fu);
-  h ^= h >> 15;
-  h *= 0x2C1B3C6Du;
+  const uint32_t a = (uint32_t)lo, b = (uint32_t)(lo >> 32), c = (uint32_t)hi, d = (uint32_t)(hi >> 32);
+  uint32_t h = (a ^ __builtin_amdgcn_alignbit(b, b, 21)) + (c ^ __builtin_amdgcn_alignbit(d, d, 13));
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
   h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
   return h;
 }
 
