@@ -1056,13 +1056,36 @@ struct RedTable {
   uint32_t cap;
 };
 
+// Bits of the word hash for the pass-2 table: the partition fixes bits 0-7, so the tag takes
+// bits 8-26 and the group bits 21-31.
+WC_DEV uint32_t red_tag(uint32_t h) { return ((h >> 8) & 0x7ffffu) | 1u; }
+WC_DEV uint32_t red_group(uint32_t h) { return h >> 21; }
+
+// The common case: the word has an entry, found by the first tag match of its home group.
+// Counts it and returns true; false sends the word to red_add.
+WC_DEV bool red_hit(const RedTable& T, const uint4 want, uint32_t h) {
+  const uint32_t tag = red_tag(h);
+  const uint4 s4 = ((const uint4*)T.slot)[red_group(h)];
+  const uint32_t e = (s4.x >> 13) == tag   ? s4.x
+                     : (s4.y >> 13) == tag ? s4.y
+                     : (s4.z >> 13) == tag ? s4.z
+                     : (s4.w >> 13) == tag ? s4.w
+                                           : 0u;
+  if (e == 0) return false;
+  const uint32_t idx = e & 0x1fffu;
+  const uint4 k = T.key[idx];
+  if (k.x != want.x || k.y != want.y || k.z != want.z || k.w != want.w) return false;
+  atomicAdd(&T.cnt[idx], 1u);
+  return true;
+}
+
 // Add one occurrence. Returns false when the word has no entry and none can be made (entries
 // exhausted or 16 groups probed): the caller counts it in the global table.
 WC_DEV bool red_add(const RedTable& T, uint64_t lo, uint64_t hi, uint32_t h) {
   constexpr uint32_t kGroups = kRedSlots / 4;
   constexpr uint32_t kNoEntry = 0xffffffffu;
-  const uint32_t tag = (h & 0x7ffffu) | 1u;
-  uint32_t g = h >> (32 - 11);  // 11 bits: kGroups groups
+  const uint32_t tag = red_tag(h);
+  uint32_t g = red_group(h);
   static_assert(kGroups == 2048, "group index takes the hash's top 11 bits");
   const uint4 want = key4(lo, hi);
   uint32_t mine = kNoEntry, probe = 0;
@@ -1176,15 +1199,26 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   constexpr uint32_t kPerIter = BLOCK / kBlockRec;  // blocks per iteration
   static_assert(BLOCK % kBlockRec == 0, "whole blocks per iteration");
   const uint32_t r_in = tid % kBlockRec, b_in = tid / kBlockRec;
-  auto add_record = [&](const uint4 v) {
-    const uint64_t lo = (uint64_t)v.x | ((uint64_t)v.y << 32);
-    const uint64_t hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
-    // every record of this partition has the same low 8 hash bits: mix before splitting
-    const bool ok = red_add(T, lo, hi, word_hash32(lo, hi) * 0x9E3779B1u);
-    if (!ok) {
-      atomicAdd(&s_miss, 1u);
-      table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
-                          short_id(lo, hi, 0), 1, hdr, P.occ_limit);
+  // up to two records per lane: the common case for both, then the rest one at a time
+  auto add_records = [&](const uint4 va, bool ua, const uint4 vb, bool ub) {
+    const uint64_t loa = (uint64_t)va.x | ((uint64_t)va.y << 32), hia = (uint64_t)va.z | ((uint64_t)va.w << 32);
+    const uint64_t lob = (uint64_t)vb.x | ((uint64_t)vb.y << 32), hib = (uint64_t)vb.z | ((uint64_t)vb.w << 32);
+    const uint32_t ha = word_hash32(loa, hia), hb = word_hash32(lob, hib);
+    const bool da = ua && !red_hit(T, va, ha);
+    const bool db = ub && !red_hit(T, vb, hb);
+    if (__any(da)) {
+      if (da && !red_add(T, loa, hia, ha)) {
+        atomicAdd(&s_miss, 1u);
+        table_insert<false>(P.table, P.mask, short_key_g<false>(loa, hia, P.key_mask),
+                            short_id(loa, hia, 0), 1, hdr, P.occ_limit);
+      }
+    }
+    if (__any(db)) {
+      if (db && !red_add(T, lob, hib, hb)) {
+        atomicAdd(&s_miss, 1u);
+        table_insert<false>(P.table, P.mask, short_key_g<false>(lob, hib, P.key_mask),
+                            short_id(lob, hib, 0), 1, hdr, P.occ_limit);
+      }
     }
   };
   for (uint32_t w0 = 0; w0 < nblk; w0 += kWinBlocks) {
@@ -1202,27 +1236,31 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
     __syncthreads();
     const uint32_t nl = s_nlist;
     if (nl == 0) continue;
-    // Records arrive kDepth iterations ahead in a register ring that is never rotated (a move
-    // of a register with a load in flight would wait for it): the loop is unrolled by kDepth.
+    // A thread takes record r_in of list entries e and e + kPerIter per iteration. Records
+    // arrive kDepth iterations ahead in register rings that are never rotated (a move of a
+    // register with a load in flight would wait for it): the loop is unrolled by kDepth.
     // Loads never branch: past the list's end they read its first block and count nothing.
     constexpr int kDepth = 4;
-    uint4 v[kDepth];
-    uint32_t f[kDepth];
+    constexpr uint32_t kStep = 2 * kPerIter;
+    uint4 va[kDepth], vb[kDepth];
+    uint32_t fa[kDepth], fb[kDepth];
+    auto load = [&](uint32_t e, uint4& v, uint32_t& f) {
+      const uint32_t ee = e < nl ? e : 0u;
+      f = e < nl ? s_lfill[ee] : 0u;
+      v = region[(uint64_t)(w0 + s_list[ee]) * kBlockRec + r_in];
+    };
 #pragma unroll
     for (int jj = 0; jj < kDepth; ++jj) {
-      const uint32_t e = jj * kPerIter + b_in;
-      const uint32_t ee = e < nl ? e : 0u;
-      f[jj] = e < nl ? s_lfill[ee] : 0u;
-      v[jj] = region[(uint64_t)(w0 + s_list[ee]) * kBlockRec + r_in];
+      load(jj * kStep + b_in, va[jj], fa[jj]);
+      load(jj * kStep + kPerIter + b_in, vb[jj], fb[jj]);
     }
-    for (uint32_t e0 = 0; e0 < nl; e0 += kDepth * kPerIter) {
+    for (uint32_t e0 = 0; e0 < nl; e0 += kDepth * kStep) {
 #pragma unroll
       for (int jj = 0; jj < kDepth; ++jj) {
-        if (r_in < f[jj]) add_record(v[jj]);
-        const uint32_t e = e0 + (jj + kDepth) * kPerIter + b_in;
-        const uint32_t ee = e < nl ? e : 0u;
-        f[jj] = e < nl ? s_lfill[ee] : 0u;
-        v[jj] = region[(uint64_t)(w0 + s_list[ee]) * kBlockRec + r_in];
+        add_records(va[jj], r_in < fa[jj], vb[jj], r_in < fb[jj]);
+        const uint32_t e = e0 + (jj + kDepth) * kStep + b_in;
+        load(e, va[jj], fa[jj]);
+        load(e + kPerIter, vb[jj], fb[jj]);
       }
     }
     __syncthreads();  // the list is rebuilt for the next window
