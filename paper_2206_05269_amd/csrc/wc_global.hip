@@ -1199,25 +1199,27 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   constexpr uint32_t kPerIter = BLOCK / kBlockRec;  // blocks per iteration
   static_assert(BLOCK % kBlockRec == 0, "whole blocks per iteration");
   const uint32_t r_in = tid % kBlockRec, b_in = tid / kBlockRec;
-  // up to two records per lane: the common case for both, then the rest one at a time
-  auto add_records = [&](const uint4 va, bool ua, const uint4 vb, bool ub) {
-    const uint64_t loa = (uint64_t)va.x | ((uint64_t)va.y << 32), hia = (uint64_t)va.z | ((uint64_t)va.w << 32);
-    const uint64_t lob = (uint64_t)vb.x | ((uint64_t)vb.y << 32), hib = (uint64_t)vb.z | ((uint64_t)vb.w << 32);
-    const uint32_t ha = word_hash32(loa, hia), hb = word_hash32(lob, hib);
-    const bool da = ua && !red_hit(T, va, ha);
-    const bool db = ub && !red_hit(T, vb, hb);
-    if (__any(da)) {
-      if (da && !red_add(T, loa, hia, ha)) {
-        atomicAdd(&s_miss, 1u);
-        table_insert<false>(P.table, P.mask, short_key_g<false>(loa, hia, P.key_mask),
-                            short_id(loa, hia, 0), 1, hdr, P.occ_limit);
-      }
-    }
-    if (__any(db)) {
-      if (db && !red_add(T, lob, hib, hb)) {
-        atomicAdd(&s_miss, 1u);
-        table_insert<false>(P.table, P.mask, short_key_g<false>(lob, hib, P.key_mask),
-                            short_id(lob, hib, 0), 1, hdr, P.occ_limit);
+  // kRec records per lane at once: the common case for all of them, then the rest one at a time
+  constexpr int kRec = 4;
+  auto add_records = [&](const uint4* v, const bool* use) {
+    uint32_t h[kRec];
+    bool d[kRec];
+#pragma unroll
+    for (int x = 0; x < kRec; ++x)
+      h[x] = word_hash32((uint64_t)v[x].x | ((uint64_t)v[x].y << 32),
+                         (uint64_t)v[x].z | ((uint64_t)v[x].w << 32));
+#pragma unroll
+    for (int x = 0; x < kRec; ++x) d[x] = use[x] && !red_hit(T, v[x], h[x]);
+#pragma unroll
+    for (int x = 0; x < kRec; ++x) {
+      if (__any(d[x])) {
+        const uint64_t lo = (uint64_t)v[x].x | ((uint64_t)v[x].y << 32);
+        const uint64_t hi = (uint64_t)v[x].z | ((uint64_t)v[x].w << 32);
+        if (d[x] && !red_add(T, lo, hi, h[x])) {
+          atomicAdd(&s_miss, 1u);
+          table_insert<false>(P.table, P.mask, short_key_g<false>(lo, hi, P.key_mask),
+                              short_id(lo, hi, 0), 1, hdr, P.occ_limit);
+        }
       }
     }
   };
@@ -1236,31 +1238,33 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
     __syncthreads();
     const uint32_t nl = s_nlist;
     if (nl == 0) continue;
-    // A thread takes record r_in of list entries e and e + kPerIter per iteration. Records
-    // arrive kDepth iterations ahead in register rings that are never rotated (a move of a
-    // register with a load in flight would wait for it): the loop is unrolled by kDepth.
+    // A thread takes record r_in of list entries e + x * kPerIter (x < kRec) per iteration.
+    // Records arrive kDepth iterations ahead in register rings that are never rotated (a move
+    // of a register with a load in flight would wait for it): the loop is unrolled by kDepth.
     // Loads never branch: past the list's end they read its first block and count nothing.
-    constexpr int kDepth = 4;
-    constexpr uint32_t kStep = 2 * kPerIter;
-    uint4 va[kDepth], vb[kDepth];
-    uint32_t fa[kDepth], fb[kDepth];
-    auto load = [&](uint32_t e, uint4& v, uint32_t& f) {
+    constexpr int kDepth = 2;
+    constexpr uint32_t kStep = kRec * kPerIter;
+    uint4 v[kDepth][kRec];
+    uint32_t f[kDepth][kRec];
+    auto load = [&](uint32_t e, uint4& vv, uint32_t& ff) {
       const uint32_t ee = e < nl ? e : 0u;
-      f = e < nl ? s_lfill[ee] : 0u;
-      v = region[(uint64_t)(w0 + s_list[ee]) * kBlockRec + r_in];
+      ff = e < nl ? s_lfill[ee] : 0u;
+      vv = region[(uint64_t)(w0 + s_list[ee]) * kBlockRec + r_in];
     };
 #pragma unroll
-    for (int jj = 0; jj < kDepth; ++jj) {
-      load(jj * kStep + b_in, va[jj], fa[jj]);
-      load(jj * kStep + kPerIter + b_in, vb[jj], fb[jj]);
-    }
+    for (int jj = 0; jj < kDepth; ++jj)
+#pragma unroll
+      for (int x = 0; x < kRec; ++x) load(jj * kStep + x * kPerIter + b_in, v[jj][x], f[jj][x]);
     for (uint32_t e0 = 0; e0 < nl; e0 += kDepth * kStep) {
 #pragma unroll
       for (int jj = 0; jj < kDepth; ++jj) {
-        add_records(va[jj], r_in < fa[jj], vb[jj], r_in < fb[jj]);
+        bool use[kRec];
+#pragma unroll
+        for (int x = 0; x < kRec; ++x) use[x] = r_in < f[jj][x];
+        add_records(v[jj], use);
         const uint32_t e = e0 + (jj + kDepth) * kStep + b_in;
-        load(e, va[jj], fa[jj]);
-        load(e + kPerIter, vb[jj], fb[jj]);
+#pragma unroll
+        for (int x = 0; x < kRec; ++x) load(e + x * kPerIter, v[jj][x], f[jj][x]);
       }
     }
     __syncthreads();  // the list is rebuilt for the next window
