@@ -756,20 +756,25 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   uint32_t spilled = 0, direct = 0, waits = 0;
   bool stalled = false;
 
-  // One pass over up to 8 owned chunks (owners of slot a first, then of slot b), 8 lanes (one
-  // record each) per chunk; oval = (partition << 16) | last ticket. Chunks that are not ready
-  // stay owned.
-  auto flush_pass = [&](bool& own_a, bool& own_b, uint32_t oval_a, uint32_t oval_b) {
+  // One pass over up to 8 owned chunks, 8 lanes (one record each) per chunk; oval = (partition
+  // << 16) | last ticket. The owners are ranked (slot a first, then slot b) and the pass takes
+  // ranks rot, rot + 1, ... (mod the number of owners): successive passes of a wait turn the
+  // window, so every owned chunk gets its turn. Chunks that are not ready stay owned.
+  auto flush_pass = [&](bool& own_a, bool& own_b, uint32_t oval_a, uint32_t oval_b,
+                        uint32_t rot) {
     const uint64_t oma = __ballot(own_a), omb = __ballot(own_b);
-    const uint32_t na = (uint32_t)__popcll(oma);
-    const uint32_t ia = __builtin_amdgcn_mbcnt_hi((uint32_t)(oma >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)oma, 0u));
-    const uint32_t ib = na + __builtin_amdgcn_mbcnt_hi((uint32_t)(omb >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)omb, 0u));
+    const uint32_t na = (uint32_t)__popcll(oma), no = na + (uint32_t)__popcll(omb);
+    if (rot) rot %= no;  // rot = 0 on a wait's first pass
+    uint32_t ia = __builtin_amdgcn_mbcnt_hi((uint32_t)(oma >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)oma, 0u));
+    uint32_t ib = na + __builtin_amdgcn_mbcnt_hi((uint32_t)(omb >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)omb, 0u));
+    ia = ia >= rot ? ia - rot : ia + no - rot;
+    ib = ib >= rot ? ib - rot : ib + no - rot;
     if (own_a && ia < 8) s_dq[wv][ia] = oval_a;
     if (own_b && ib < 8) s_dq[wv][ib] = oval_b;
     wave_sync();
-    const uint32_t nc = min(na + (uint32_t)__popcll(omb), 8u);
+    const uint32_t nc = min(no, 8u);
     const uint32_t g = lane >> 3, j = lane & 7;
     bool ok = false;
     uint32_t q = 0, start = 0, slot = 0;
@@ -883,7 +888,7 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
       // a chunk can leave only once the owner's own record is in it
       bool fa2 = own_a && !pend_a, fb2 = own_b && !pend_b;
       if (__any(fa2 || fb2)) {
-        flush_pass(fa2, fb2, (pa << 16) | tka, (pb << 16) | tkb);
+        flush_pass(fa2, fb2, (pa << 16) | tka, (pb << 16) | tkb, 8 * (spins - 1));
         own_a = own_a && (pend_a || fa2);
         own_b = own_b && (pend_b || fb2);
       }
@@ -1088,7 +1093,7 @@ WC_DEV bool red_add(const RedTable& T, uint64_t lo, uint64_t hi, uint32_t h) {
   uint32_t g = red_group(h);
   static_assert(kGroups == 2048, "group index takes the hash's top 11 bits");
   const uint4 want = key4(lo, hi);
-  uint32_t mine = kNoEntry, probe = 0;
+  uint32_t mine = kNoEntry, probe = 0, waits = 0;
   bool active = true, ok = false;
   while (__any(active)) {
     if (active) {
@@ -1116,7 +1121,9 @@ WC_DEV bool red_add(const RedTable& T, uint64_t lo, uint64_t hi, uint32_t h) {
         ok = true;
         active = false;
       } else if (wait) {
-        // look at this group again
+        // look at this group again. A key is written before its slot is claimed, so a claimed
+        // slot shows a zero key only for a zero record, which no word makes: give up on it
+        if (++waits >= 4096) active = false;
       } else if (free_j >= 0) {
         if (mine == kNoEntry) {
           const uint32_t m = atomicAdd(T.n, 1u);
