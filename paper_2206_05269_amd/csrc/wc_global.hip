@@ -777,22 +777,24 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     const uint32_t nc = min(no, 8u);
     const uint32_t g = lane >> 3, j = lane & 7;
     bool ok = false;
-    uint32_t q = 0, start = 0, slot = 0;
+    uint32_t q = 0, start = 0, slot = 0, gb = 0;
     uint4 r4 = make_uint4(0, 0, 0, 0);
     if (g < nc) {
       const uint32_t v = s_dq[wv][g];
       q = v >> 16;
       start = (v - (kChunkRec - 1)) & 0xffffu;
-      // head first: once it has reached the chunk, the slots hold the chunk's records or 0
+      // head first: once it has reached the chunk, the slots hold the chunk's records or 0,
+      // and the partition's block is the one the chunk before left
       const uint32_t head =
           __hip_atomic_load(&s_fill[q], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >> 16;
       slot = q * kStageSlots + ((start + j) & kRingMask);
       r4 = s_stage[slot];
+      gb = s_blk[q];
       ok = head == start && r4.x != 0;
     }
     const uint64_t okm = __ballot(ok);
     if (g < nc && ((okm >> (8 * g)) & 0xffull) == 0xffull) {
-      const uint32_t gb = s_blk[q], bp = start & (kBlockRec - 1);
+      const uint32_t bp = start & (kBlockRec - 1);
       if (gb != kNone) {
         P.arena[(uint64_t)gb * kBlockRec + bp + j] = r4;
       } else {
