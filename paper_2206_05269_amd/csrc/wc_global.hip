@@ -1063,9 +1063,15 @@ struct RedTable {
   uint32_t cap;
 };
 
-// Bits of the word hash for the pass-2 table: the partition fixes bits 0-7, so the tag takes
-// bits 8-26 and the group bits 21-31.
-WC_DEV uint32_t red_tag(uint32_t h) { return ((h >> 8) & 0x7ffffu) | 1u; }
+// Hash of a record for the pass-2 table (the word hash is useless here: its low 8 bits are the
+// partition's): the dwords folded with rotations and one multiply; the group is the top 11
+// bits, the tag 19 bits below them.
+WC_DEV uint32_t red_hash(const uint4 v) {
+  const uint32_t x = (v.x ^ __builtin_amdgcn_alignbit(v.y, v.y, 11)) +
+                     (v.z ^ __builtin_amdgcn_alignbit(v.w, v.w, 23));
+  return (x ^ (x >> 15)) * 0x9E3779B1u;
+}
+WC_DEV uint32_t red_tag(uint32_t h) { return ((h >> 2) & 0x7ffffu) | 1u; }
 WC_DEV uint32_t red_group(uint32_t h) { return h >> 21; }
 
 // The common case: the word has an entry, found by the first tag match of its home group.
@@ -1207,7 +1213,11 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   const uint16_t* fills = P.fill + (uint64_t)p * P.R;
   constexpr uint32_t kPerIter = BLOCK / kBlockRec;  // blocks per iteration
   static_assert(BLOCK % kBlockRec == 0, "whole blocks per iteration");
-  const uint32_t r_in = tid % kBlockRec, b_in = tid / kBlockRec;
+  // b_in is the same for a whole wave (a block is 4 waves): list reads and block addresses
+  // are scalar
+  const uint32_t r_in = tid % kBlockRec;
+  const uint32_t b_in = (uint32_t)__builtin_amdgcn_readfirstlane(tid / kBlockRec);
+  static_assert(kBlockRec % 64 == 0, "a block spans whole waves");
   // kRec records per lane at once: the common case for all of them, then the rest one at a time
   constexpr int kRec = 4;
   auto add_records = [&](const uint4* v, const bool* use) {
@@ -1215,8 +1225,7 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
     bool d[kRec];
 #pragma unroll
     for (int x = 0; x < kRec; ++x)
-      h[x] = word_hash32((uint64_t)v[x].x | ((uint64_t)v[x].y << 32),
-                         (uint64_t)v[x].z | ((uint64_t)v[x].w << 32));
+      h[x] = red_hash(v[x]);
 #pragma unroll
     for (int x = 0; x < kRec; ++x) d[x] = use[x] && !red_hit(T, v[x], h[x]);
 #pragma unroll
