@@ -308,8 +308,10 @@ WC_DEV uint32_t compact_starts(uint32_t start16, uint32_t* s_wsum, uint16_t* s_s
 // ---------------------------------------------------------------------------------------
 // dictionary: sample, threshold, placement
 // ---------------------------------------------------------------------------------------
-// One stage per workgroup, spread evenly over the text. Document boundaries are ignored and
-// words cut at the stage edges count as they appear: the sample only ranks words.
+// kSamplePer stages per workgroup, all spread evenly over the text; the workgroup counts them
+// in one LDS table and adds it to the sample table once (fewer workgroups adding the same hot
+// words). Document boundaries are ignored and words cut at the stage edges count as they
+// appear: the sample only ranks words.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void sample_kernel(GlobalParams P) {
   constexpr int STAGE = BLOCK * 16;
@@ -324,53 +326,57 @@ __global__ __launch_bounds__(BLOCK) void sample_kernel(GlobalParams P) {
   const int tid = threadIdx.x;
   if (ld_relaxed32(&P.hdr->flags) & kFlagBadOffsets) return;
   const int64_t R0 = (int64_t)P.offsets[0], R1 = (int64_t)P.offsets[P.n_docs];
-  const uint64_t k = (uint64_t)blockIdx.x * P.n_stages / gridDim.x;
-  const int64_t ls = P.base_off + (int64_t)(k * kGlobalStage);  // first STAGE bytes of it
-  uint32_t w16;
-  uint4 g = classify16(load_text16(P.corpus, P.len, ls + tid * 16), &w16);
-  w16 = cut16(w16, ls + tid * 16, R0, R1);
-  s_txt4[tid] = g;
-  s_wm[tid] = (uint16_t)w16;
-  if (tid < 2) s_txt4[BLOCK + tid] = make_uint4(0, 0, 0, 0);
-  if (tid == 0) {
-    s_live = 0;
-    s_last[BLOCK] = 0;
-  }
   LdsWords T{s_lo, s_hi, s_cnt, kSampleLds};
   for (uint32_t i = tid; i < kSampleLds; i += BLOCK) {
     s_lo[i] = 0;
     s_hi[i] = 0;
     s_cnt[i] = 0;
   }
-  __syncthreads();
-  const uint32_t prev = tid > 0 ? (s_wm[tid - 1] >> 15) : 0u;
-  const uint32_t next = tid < BLOCK - 1 ? (s_wm[tid + 1] & 1u) : 0u;
-  const uint32_t start16 = w16 & ~((w16 << 1) | prev) & 0xffffu;
-  const uint32_t last16 = w16 & ~((w16 >> 1) | (next << 15)) & 0xffffu;
-  s_last[tid] = (uint16_t)last16;
-  uint32_t rank0;
-  // without document boundaries a start follows a delimiter, so a stage has <= STAGE / 2
-  const uint32_t total =
-      min(compact_starts<BLOCK>(start16, s_wsum, s_starts, STAGE / 2, &rank0), (uint32_t)STAGE / 2);
+  if (tid < 2) s_txt4[BLOCK + tid] = make_uint4(0, 0, 0, 0);
+  if (tid == 0) {
+    s_live = 0;
+    s_last[BLOCK] = 0;
+  }
   const uint32_t cap = kSampleLds - kSampleLds / 4;
-  for (uint32_t t = tid; t < total; t += BLOCK) {
-    const uint32_t s = s_starts[t];
-    uint32_t q = s >> 4;
-    uint32_t bits = (uint32_t)s_last[q] >> (s & 15);
-    uint32_t e;
-    if (bits) {
-      e = s + __ffs(bits) - 1;
-    } else {
-      ++q;
-      while (q < BLOCK && s_last[q] == 0) ++q;  // the stage's last word byte ends a word
-      if (q >= BLOCK) continue;
-      e = q * 16 + __ffs(s_last[q]) - 1;
+  const uint64_t n_sampled = (uint64_t)gridDim.x * kSamplePer;
+  for (uint32_t it = 0; it < kSamplePer; ++it) {
+    const uint64_t k = ((uint64_t)blockIdx.x * kSamplePer + it) * P.n_stages / n_sampled;
+    const int64_t ls = P.base_off + (int64_t)(k * kGlobalStage);  // first STAGE bytes of it
+    uint32_t w16;
+    const uint4 g = classify16(load_text16(P.corpus, P.len, ls + tid * 16), &w16);
+    w16 = cut16(w16, ls + tid * 16, R0, R1);
+    __syncthreads();  // the previous stage's tokens are done with the staged text
+    s_txt4[tid] = g;
+    s_wm[tid] = (uint16_t)w16;
+    __syncthreads();
+    const uint32_t prev = tid > 0 ? (s_wm[tid - 1] >> 15) : 0u;
+    const uint32_t next = tid < BLOCK - 1 ? (s_wm[tid + 1] & 1u) : 0u;
+    const uint32_t start16 = w16 & ~((w16 << 1) | prev) & 0xffffu;
+    const uint32_t last16 = w16 & ~((w16 >> 1) | (next << 15)) & 0xffffu;
+    s_last[tid] = (uint16_t)last16;
+    uint32_t rank0;
+    // without document boundaries a start follows a delimiter, so a stage has <= STAGE / 2
+    const uint32_t total = min(compact_starts<BLOCK>(start16, s_wsum, s_starts, STAGE / 2, &rank0),
+                               (uint32_t)STAGE / 2);
+    for (uint32_t t = tid; t < total; t += BLOCK) {
+      const uint32_t s = s_starts[t];
+      uint32_t q = s >> 4;
+      uint32_t bits = (uint32_t)s_last[q] >> (s & 15);
+      uint32_t e;
+      if (bits) {
+        e = s + __ffs(bits) - 1;
+      } else {
+        ++q;
+        while (q < BLOCK && s_last[q] == 0) ++q;  // the stage's last word byte ends a word
+        if (q >= BLOCK) continue;
+        e = q * 16 + __ffs(s_last[q]) - 1;
+      }
+      const uint32_t wl = e - s + 1;
+      if (wl > 16) continue;
+      uint64_t lo, hi;
+      pack_word((const uint8_t*)s_txt4, s, wl, &lo, &hi);
+      lds_add(T, lo, hi, word_hash32(lo, hi), 1, s_live < cap, &s_live);
     }
-    const uint32_t wl = e - s + 1;
-    if (wl > 16) continue;
-    uint64_t lo, hi;
-    pack_word((const uint8_t*)s_txt4, s, wl, &lo, &hi);
-    lds_add(T, lo, hi, word_hash32(lo, hi), 1, s_live < cap, &s_live);
   }
   __syncthreads();
   for (uint32_t i = tid; i < kSampleLds; i += BLOCK) {
@@ -1325,7 +1331,8 @@ hipError_t set_global_smem(uint32_t dict_cap, uint32_t reduce_entries) {
 
 hipError_t launch_global(const GlobalParams& P, hipEvent_t a, hipEvent_t b, hipStream_t s) {
   const uint32_t ns = (uint32_t)(P.n_stages < kSampleStages ? P.n_stages : kSampleStages);
-  if (ns) hipLaunchKernelGGL(sample_kernel<512>, dim3(ns), dim3(512), 0, s, P);
+  if (ns) hipLaunchKernelGGL(sample_kernel<512>, dim3((ns + kSamplePer - 1) / kSamplePer), dim3(512),
+                             0, s, P);
   hipLaunchKernelGGL(dict_hist_kernel, dim3(256), dim3(256), 0, s, P);
   hipLaunchKernelGGL(dict_select_kernel, dim3(256), dim3(256), 0, s, P);
   hipLaunchKernelGGL(dict_build_kernel, dim3(1), dim3(1024), 0, s, P);

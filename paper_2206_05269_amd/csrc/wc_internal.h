@@ -42,7 +42,8 @@ constexpr uint32_t kDispBuckets = 512;   // dictionary: displacement buckets (lo
 constexpr uint32_t kDictSlots = 4096;    // dictionary: slots of the perfect hash
 constexpr uint32_t kDictRegions = 16;    // dictionary: regions of 256 slots (group mod 16)
 constexpr uint32_t kSampleStages = 512;  // pass-1 stages sampled (first 8 KiB of each)
-constexpr uint32_t kSampleLds = 2048;    // LDS table of one sampled stage
+constexpr uint32_t kSamplePer = 2;       // sampled stages per sample workgroup
+constexpr uint32_t kSampleLds = 2048;    // LDS table of one sample workgroup
 constexpr uint64_t kSampleSlots = 1ull << 19;  // device table of the sample
 constexpr uint32_t kStripe = 1024;       // pass-1 bytes per wave per stage
 constexpr uint32_t kStripeText = kStripe + 16;  // staged per wave: the stripe and 16 bytes after
