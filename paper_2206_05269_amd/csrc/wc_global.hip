@@ -459,6 +459,7 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
   constexpr uint32_t kRegionGroups = kDispBuckets / kDictRegions;
   static_assert(kDictSlots == kDictRegions * 256 && kRegionGroups <= 64, "256-slot regions");
   __shared__ uint32_t s_h[kDictMax];
+  __shared__ uint8_t s_c8[kDictMax];      // sample counts (clamped at 255)
   __shared__ uint16_t s_gkeys[kDictMax];  // key indices grouped by group, hottest first
   __shared__ uint32_t s_gn[kDispBuckets], s_gstart[kDispBuckets];
   __shared__ uint8_t s_ord[kDictRegions][kRegionGroups];
@@ -487,6 +488,7 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
     const uint32_t h = word_hash32((uint64_t)k.x | ((uint64_t)k.y << 32),
                                    (uint64_t)k.z | ((uint64_t)k.w << 32));
     s_h[i] = h;
+    s_c8[i] = (uint8_t)P.dict->cnt[i];
     atomicAdd(&s_gn[dict_group(h)], 1u);
   }
   __syncthreads();
@@ -513,9 +515,9 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
     const uint32_t m = s_gn[g];
     for (uint32_t x = 1; x < m; ++x) {
       const uint16_t v = a[x];
-      const uint32_t cv = P.dict->cnt[v];
+      const uint32_t cv = s_c8[v];
       uint32_t y = x;
-      while (y > 0 && P.dict->cnt[a[y - 1]] < cv) {
+      while (y > 0 && s_c8[a[y - 1]] < cv) {
         a[y] = a[y - 1];
         --y;
       }
