@@ -645,7 +645,7 @@ WC_DEV uint32_t load_text4(const uint8_t* corpus, uint64_t len, int64_t p) {
 // else kLongEnd (the word runs past the next lane's bytes: longer than 16 bytes).
 WC_DEV void write_pairs(uint32_t m, uint32_t last16, uint32_t nl, uint32_t rank, uint32_t w0,
                         uint32_t* pairs) {
-  const uint32_t pos0 = (threadIdx.x & 63) * 16;
+  const uint32_t pos0 = 16 + (threadIdx.x & 63) * 16;  // after the 16-byte prefix
   while (m) {
     const uint32_t j = __ffs(m) - 1;
     if (rank - w0 < kWaveStarts) {
@@ -906,65 +906,54 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     waits += spins > 1 ? spins - 1 : 0;
   };
 
-  auto stripe_pos = [&](uint64_t k) -> int64_t {
-    return P.base_off + (int64_t)(k * STAGE) + (int64_t)wv * kStripe;
+  // Wave wv scans its own contiguous run of nsw stripes of the workgroup's range. The word
+  // byte before a stripe and the word that runs over a stripe's end come from the wave's
+  // previous stripe: its last 16 bytes stay in LDS as the prefix of the next stripe's text
+  // (my_txt: 16-byte prefix, the stripe, 16 bytes of padding), and such a word is finished by
+  // the next stripe.
+  const uint64_t nsw = st1 > st0 ? st1 - st0 : 0;
+  const uint64_t sw0 = st0 * NW + (uint64_t)wv * nsw;
+  auto stripe_pos = [&](uint64_t i) -> int64_t {
+    return P.base_off + (int64_t)((sw0 + i) * kStripe);
   };
-  auto load_main = [&](uint64_t k) -> uint4 {
-    return load_text16(P.corpus, P.len, stripe_pos(k) + lane * 16);
-  };
-  // lanes 0-3: the 16 bytes after the stripe; lane 4: the 4 bytes before it
-  auto load_side = [&](uint64_t k) -> uint32_t {
-    const int64_t p0 = stripe_pos(k);
-    return lane < 5 ? load_text4(P.corpus, P.len, lane < 4 ? p0 + kStripe + lane * 4 : p0 - 4)
-                    : 0x20202020u;
+  auto load_main = [&](uint64_t i) -> uint4 {
+    return load_text16(P.corpus, P.len, stripe_pos(i) + lane * 16);
   };
 
   const uint4 blank = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);
   uint4 cur = blank, nx = blank;
-  uint32_t side = 0x20202020u, side_nx = 0x20202020u;
-  if (st0 < st1) {
-    cur = load_main(st0);
-    side = load_side(st0);
+  uint32_t carry = 0;  // the byte before the stripe is a word byte (wave-uniform)
+  if (nsw > 0) {
+    cur = load_main(0);
+    const int64_t q = stripe_pos(0) - 1;
+    uint32_t f;
+    fold_classify4(load_text4(P.corpus, P.len, q - 3), &f);
+    carry = (q >= R0 && q < R1) ? f >> 31 : 0u;
   }
-  if (st0 + 1 < st1) {
-    nx = load_main(st0 + 1);
-    side_nx = load_side(st0 + 1);
-  }
+  if (nsw > 1) nx = load_main(1);
   uint64_t tokens = 0;  // wave-uniform
+  bool def = false;     // a word of the previous stripe runs over its end (wave-uniform) ...
+  uint32_t def_s = 0;   // ... from prefix byte def_s
 
-  for (uint64_t k = st0; k < st1; ++k) {
-    const int64_t p0 = stripe_pos(k);
-    // documents starting in [p0, p0 + kStripeText): the first at or after the stage start is
-    // stage_doc[k]; the bytes after the last stripe of a stage lie in the next stage
-    const uint64_t c0 = P.stage_doc[k];
-    const uint64_t c2 = P.stage_doc[min(k + (wv == NW - 1 ? 2 : 1), n_stages)];
-    const bool plain = c2 == c0 && p0 >= R0 && p0 + (int64_t)kStripeText <= R1;
+  for (uint64_t i = 0; i < nsw; ++i) {
+    const int64_t p0 = stripe_pos(i);
+    const uint64_t stage = (sw0 + i) / NW;
+    // documents starting in [p0, p0 + kStripe): the first at or after the stage start is
+    // stage_doc[stage]
+    const uint64_t c0 = P.stage_doc[stage];
+    const uint64_t c2 = P.stage_doc[min(stage + 1, n_stages)];
+    const bool plain = c2 == c0 && p0 >= R0 && p0 + (int64_t)kStripe <= R1;
 
-    // ---- classify; the word bytes just after and before the stripe -----------------------
+    // ---- classify ---------------------------------------------------------------------------
     uint32_t w16;
     const uint4 g = classify16(cur, &w16);
     if (!plain) w16 = cut16(w16, p0 + lane * 16, R0, R1);
-    ((uint4*)my_txt)[lane] = g;
-    uint32_t sflag;
-    const uint32_t sg = fold_classify4(side, &sflag);
-    if (lane < 4) ((uint32_t*)my_txt)[kStripe / 4 + lane] = sg;
-    const uint32_t m4 = movemask4(sflag);
-    uint32_t nm = (uint32_t)__builtin_amdgcn_readlane((int)m4, 0) |
-                  ((uint32_t)__builtin_amdgcn_readlane((int)m4, 1) << 4) |
-                  ((uint32_t)__builtin_amdgcn_readlane((int)m4, 2) << 8) |
-                  ((uint32_t)__builtin_amdgcn_readlane((int)m4, 3) << 12);
-    uint32_t carry = ((uint32_t)__builtin_amdgcn_readlane((int)m4, 4) >> 3) & 1u;
-    if (p0 - 1 < R0 || p0 - 1 >= R1) carry = 0;
-    if (!plain) nm = cut16(nm, p0 + kStripe, R0, R1);
+    ((uint4*)my_txt)[1 + lane] = g;
     cur = nx;
-    side = side_nx;
-    if (k + 2 < st1) {
-      nx = load_main(k + 2);
-      side_nx = load_side(k + 2);
-    }
+    if (i + 2 < nsw) nx = load_main(i + 2);
 
     // ---- document starts of the stripe ---------------------------------------------------
-    uint32_t bnd16 = 0, bnext = 0, bnd64 = 0;
+    uint32_t bnd16 = 0, bnext = 0;
     if (!plain) {
       if (c2 > c0) {
         uint64_t j0 = c0, j1 = c2;
@@ -976,48 +965,76 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
         for (uint64_t jb = j0; jb < c2; jb += 64) {
           const uint64_t j = jb + lane;
           const int64_t o = j < c2 ? (int64_t)P.offsets[j] : INT64_MAX;
-          if (o >= p0 && o < p0 + (int64_t)kStripeText) {
+          if (o >= p0 && o < p0 + (int64_t)kStripe) {
             const uint32_t rel = (uint32_t)(o - p0);
             atomicOr(&my_bnd[rel >> 5], 1u << (rel & 31));
           }
-          if (__all(o >= p0 + (int64_t)kStripeText)) break;
+          if (__all(o >= p0 + (int64_t)kStripe)) break;
         }
         wave_sync();
       }
       bnd16 = (my_bnd[lane >> 1] >> ((lane & 1) * 16)) & 0xffffu;
-      bnext = (my_bnd[(lane + 1) >> 1] >> (((lane + 1) & 1) * 16)) & 1u;
-      bnd64 = my_bnd[kStripe / 32] & 0xffffu;
+      bnext = (my_bnd[(lane + 1) >> 1] >> (((lane + 1) & 1) * 16)) & 1u;  // lane 63: 0
       wave_sync();
       if (lane < (int)kBndWords) my_bnd[lane] = 0;
     }
 
     // ---- word starts and ends --------------------------------------------------------------
     // previous lane's last byte (lane 0: the byte before the stripe); next lane's first byte
-    // (lane 63: the byte after the stripe)
+    // (lane 63: taken as a word byte: a word running to the stripe's end is finished by the
+    // next stripe)
     const uint32_t prev =
         (uint32_t)__builtin_amdgcn_update_dpp((int)carry, (int)(w16 >> 15), 0x138, 0xf, 0xf, false);
     const uint32_t nxt =
-        (uint32_t)__builtin_amdgcn_update_dpp((int)(nm & 1u), (int)(w16 & 1u), 0x130, 0xf, 0xf, false);
-    const uint32_t start16 = w16 & (~((w16 << 1) | prev) | bnd16) & 0xffffu;
+        (uint32_t)__builtin_amdgcn_update_dpp(1, (int)(w16 & 1u), 0x130, 0xf, 0xf, false);
+    uint32_t start16 = w16 & (~((w16 << 1) | prev) | bnd16) & 0xffffu;
     const uint32_t last16 = w16 & (~((w16 >> 1) | (nxt << 15)) | (bnd16 >> 1) | (bnext << 15)) & 0xffffu;
-    // word ends among the 16 bytes after the stripe (the last of them excluded: a word still
-    // running there is longer than 16 bytes), for the word that crosses the stripe end
-    const uint32_t last64 = nm & (~(nm >> 1) | (bnd64 >> 1)) & 0x7fffu;
     const uint32_t nl =
-        (uint32_t)__builtin_amdgcn_update_dpp((int)last64, (int)last16, 0x130, 0xf, 0xf, false);
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)last16, 0x130, 0xf, 0xf, false);
+    // lane 63's last word, when it runs to the stripe's end, is left for the next stripe
+    uint32_t ndef_j = 16;
+    if (lane == 63 && start16) {
+      const uint32_t j = 31 - __clz(start16);
+      if ((last16 >> j) == 0) {
+        ndef_j = j;
+        start16 &= ~(1u << j);
+      }
+    }
+    // the previous stripe's last word: it ends at the prefix's last byte unless it runs on
+    // into lane 0 (then at lane 0's first end, or it is longer than 16 bytes)
+    uint32_t def_pair = 0;
+    if (def) {
+      const uint32_t w0b = (uint32_t)__builtin_amdgcn_readfirstlane((int)(w16 & ~start16 & 1u));
+      const uint32_t l0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)last16);
+      const uint32_t e = w0b == 0 ? 15u : (l0 ? 16u + __builtin_ctz(l0) : kLongEnd);
+      def_pair = def_s | (e << 16);
+    }
 
     // ---- compaction and tokens, kWaveStarts at a time -------------------------------------
-    const uint32_t c = __popc(start16);
+    const uint32_t extra = (def && lane == 0) ? 1u : 0u;  // the carried word takes rank 0
+    const uint32_t c = __popc(start16) + extra;
     const uint32_t incl = wave_incl_scan(c);
     const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     tokens += n;
     for (uint32_t w0 = 0; w0 < n; w0 += kWaveStarts) {
-      write_pairs(start16, last16, nl, incl - c, w0, my_pairs);
+      if (extra && w0 == 0) my_pairs[0] = def_pair;
+      write_pairs(start16, last16, nl, incl - c + extra, w0, my_pairs);
       wave_sync();
-      token_round(min(n - w0, kWaveStarts), p0);
+      token_round(min(n - w0, kWaveStarts), p0 - 16);
       wave_sync();
     }
+    // the stripe's last 16 bytes become the next stripe's prefix
+    if (lane == 63) ((uint4*)my_txt)[0] = ((const uint4*)my_txt)[1 + 63];
+    wave_sync();
+    def = __builtin_amdgcn_readlane((int)ndef_j, 63) < 16;
+    def_s = (uint32_t)__builtin_amdgcn_readlane((int)ndef_j, 63);
+    carry = (uint32_t)__builtin_amdgcn_readlane((int)(w16 >> 15), 63);
     if (stalled) break;
+  }
+  // a word running over the range's end: from device memory
+  if (def && !stalled) {
+    tokens += 1;
+    if (lane == 0) long_token(stripe_pos(nsw) - 16, def_s, kLongEnd);
   }
   if (stalled) or32(&hdr->flags, kFlagStall);
 

@@ -46,7 +46,7 @@ constexpr uint32_t kSamplePer = 2;       // sampled stages per sample workgroup
 constexpr uint32_t kSampleLds = 2048;    // LDS table of one sample workgroup
 constexpr uint64_t kSampleSlots = 1ull << 19;  // device table of the sample
 constexpr uint32_t kStripe = 1024;       // pass-1 bytes per wave per stage
-constexpr uint32_t kStripeText = kStripe + 16;  // staged per wave: the stripe and 16 bytes after
+constexpr uint32_t kStripeText = 16 + kStripe + 16;  // per wave: prefix, stripe, padding
 constexpr uint32_t kWaveStarts = 128;    // (start, end) pairs of one wave listed at a time
 constexpr uint32_t kDictCols = 64;       // dictionary words totalled per pass-2 workgroup
 constexpr uint32_t kWinBlocks = 2048;    // pass 2 lists the non-empty blocks this many at a time
