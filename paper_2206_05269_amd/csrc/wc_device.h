@@ -298,9 +298,18 @@ WC_DEV uint64_t table_insert(Slot* __restrict__ tab, uint64_t mask, uint64_t key
       st_relaxed(&s->w0, id.w0);
       if (kPerDoc) add32((uint32_t*)&s->cnt, (uint32_t)n);
       else add64(&s->cnt, n);
-      uint64_t occ = __hip_atomic_fetch_add(&hdr->occupied, 1ull, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-      if (occ + 1 > occ_limit) or32(&hdr->flags, kFlagTableFull);
+    }
+    if (occ_limit != ~0ull) {
+      // claimed slots: one addition per wave (a single counter that every new word of every
+      // workgroup would otherwise hit); no limit, no count
+      const uint64_t wm = __ballot(won);
+      if (won && __builtin_amdgcn_mbcnt_hi((uint32_t)(wm >> 32),
+                                           __builtin_amdgcn_mbcnt_lo((uint32_t)wm, 0u)) == 0) {
+        const uint64_t c = (uint64_t)__popcll(wm);
+        uint64_t occ = __hip_atomic_fetch_add(&hdr->occupied, c, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        if (occ + c > occ_limit) or32(&hdr->flags, kFlagTableFull);
+      }
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);  // publication above stays before the reads below
     if (active) {

@@ -44,58 +44,74 @@ WC_DEV uint32_t doc_hash(uint64_t lo, uint64_t hi, uint32_t doc1) {
 }
 
 // Count n occurrences of (doc1, word). Returns false when the table cannot take it (more
-// than `cap` live entries, or no slot within the probe limit). Wave-uniform probe loop.
+// than `cap` live entries, or no slot within `max_probe` slots). Linear probing over groups of
+// 4 slots: one 32-byte read of a group's first words per step; the first empty slot ends the
+// search (no deletions while counting). Wave-uniform probe loop.
 WC_DEV bool doc_add(const DocTable& T, uint64_t lo, uint64_t hi, uint32_t doc1, uint32_t n,
                     uint32_t* live, uint32_t cap, uint32_t max_probe = 32) {
   const uint64_t hiw = hi | kTop;
-  uint32_t i = __umulhi(doc_hash(lo, hi, doc1), T.size);
-  int probe = 0;
+  const uint32_t ng = T.size >> 2;  // groups of 4 slots (T.lo is 16-byte aligned)
+  uint32_t g = __umulhi(doc_hash(lo, hi, doc1), ng);
+  uint32_t probe = 0;
   bool active = true, ok = false;
   while (__any(active)) {
-    uint64_t cur = 1;
     bool won = false;
     if (active) {
-      cur = __hip_atomic_load(&T.lo[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (cur == 0) {
-        if (__hip_atomic_load(live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < cap) {
-          cur = atomicCAS((unsigned long long*)&T.lo[i], 0ull, (unsigned long long)lo);
-          won = cur == 0;
+      const uint32_t b = g * 4;
+      const uint4 q0 = ((const uint4*)(T.lo + b))[0], q1 = ((const uint4*)(T.lo + b))[1];
+      const uint64_t v[4] = {(uint64_t)q0.x | ((uint64_t)q0.y << 32),
+                             (uint64_t)q0.z | ((uint64_t)q0.w << 32),
+                             (uint64_t)q1.x | ((uint64_t)q1.y << 32),
+                             (uint64_t)q1.z | ((uint64_t)q1.w << 32)};
+      int state = 0;  // 0: all 4 taken by other words, 1: counted, 2: empty slot e, 3: look again
+      uint32_t e = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) {
+        if (state != 0) continue;
+        if (v[j] == 0) {
+          state = 2;
+          e = b + j;
+        } else if (v[j] == lo) {
+          const uint64_t sh = __hip_atomic_load(&T.hi[b + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          const uint32_t sd = __hip_atomic_load(&T.doc1[b + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (sh == 0 || sd == 0) {
+            state = 3;  // claimed, not published yet
+          } else if (sh == hiw && sd == doc1) {
+            atomicAdd(&T.cnt[b + j], n);
+            state = 1;
+          }
         }
       }
-    }
-    if (won) {
-      __hip_atomic_store(&T.doc1[i], doc1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_store(&T.hi[i], hiw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      atomicAdd(&T.cnt[i], n);
-      atomicAdd(live, 1u);
-    }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    if (active) {
-      bool advance = true;
-      if (won) {
+      if (state == 1) {
         ok = true;
         active = false;
-        advance = false;
-      } else if (cur == 0) {
-        active = false;  // table at its cap
-        advance = false;
-      } else if (cur == lo) {
-        uint64_t sh = __hip_atomic_load(&T.hi[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        uint32_t sd = __hip_atomic_load(&T.doc1[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (sh == 0 || sd == 0) {
-          advance = false;
-        } else if (sh == hiw && sd == doc1) {
-          atomicAdd(&T.cnt[i], n);
-          ok = true;
-          active = false;
-          advance = false;
+      } else if (state == 2) {
+        if (__hip_atomic_load(live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < cap) {
+          won = atomicCAS((unsigned long long*)&T.lo[e], 0ull, (unsigned long long)lo) == 0;
+          if (won) {
+            __hip_atomic_store(&T.doc1[e], doc1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(&T.hi[e], hiw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            atomicAdd(&T.cnt[e], n);
+            ok = true;
+            active = false;
+          }  // else the slot was taken: look at this group again
+        } else {
+          active = false;  // table at its cap
         }
-      }
-      if (advance) {
-        i = (i + 1 == T.size) ? 0 : i + 1;
-        if ((uint32_t)++probe >= max_probe) active = false;
+      } else if (state == 0) {
+        g = g + 1 == ng ? 0 : g + 1;
+        probe += 4;
+        if (probe >= max_probe) active = false;
       }
     }
+    {
+      // the wave's new entries in one addition to the live count (one lane, not one per entry)
+      const uint64_t wm = __ballot(won);
+      if (wm && won && __builtin_amdgcn_mbcnt_hi((uint32_t)(wm >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)wm, 0u)) == 0)
+        atomicAdd(live, (uint32_t)__popcll(wm));
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
   return ok;
 }
@@ -141,7 +157,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   __shared__ uint16_t s_wm[BLOCK];
   __shared__ uint16_t s_last[BLOCK + 1];
   __shared__ uint32_t s_bnd[STAGE / 32 + 2];
-  __shared__ uint32_t s_buf[STAGE / 2];     // token starts (as u16)
+  __shared__ uint16_t s_starts[STAGE / 2];  // token starts
   __shared__ uint32_t s_elen[PER * BLOCK];  // emission: word lengths, then byte offsets
   __shared__ uint32_t s_wsum[NWAVE];
   __shared__ uint64_t s_doff[kDocW + 1];
@@ -151,9 +167,9 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   __shared__ uint32_t s_need[kDocW];        // a token of this document found no LDS slot
   __shared__ uint32_t s_live, s_carry[2], s_next_w;
   __shared__ uint64_t s_item, s_e0, s_b0, s_tokens, s_minpos;
+  __shared__ uint32_t s_rlo, s_rhi;  // documents of the stage: [s_rlo, s_rhi)
   __shared__ uint32_t s_emitted, s_scan_tmp[NWAVE];
   extern __shared__ __align__(16) uint8_t s_dyn[];
-  uint16_t* s_starts = (uint16_t*)s_buf;
   const uint8_t* s_txt = (const uint8_t*)s_txt4;
 
   const int tid = threadIdx.x;
@@ -503,6 +519,20 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
               atomicOr(&s_bnd[rel >> 5], 1u << (rel & 31));
             }
           }
+          if (tid == 0) {
+            // the stage's tokens belong to documents [rlo, rhi): the last one starting at or
+            // before the stage start, up to the last one starting inside the stage
+            uint32_t a = 0, b = nd;
+            while (b - a > 1) {
+              const uint32_t m = (a + b) >> 1;
+              if ((int64_t)s_doff[m] <= ls) a = m;
+              else b = m;
+            }
+            uint32_t c = a + 1;
+            while (c < nd && (int64_t)s_doff[c] < le) ++c;
+            s_rlo = a;
+            s_rhi = c;
+          }
           __syncthreads();
           uint32_t prev = tid > 0 ? (s_wm[tid - 1] >> 15) : s_carry[(k & 1) ^ 1];
           uint32_t next = tid < BLOCK - 1 ? (s_wm[tid + 1] & 1u) : s_next_w;
@@ -566,7 +596,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
               }
               // document of the token: last i with s_doff[i] <= position
               const uint64_t pos = (uint64_t)(ls + s);
-              uint32_t lo_i = 0, hi_i = nd;
+              uint32_t lo_i = s_rlo, hi_i = s_rhi;
               while (hi_i - lo_i > 1) {
                 uint32_t mid = (lo_i + hi_i) >> 1;
                 if (s_doff[mid] <= pos) lo_i = mid; else hi_i = mid;
