@@ -12,6 +12,11 @@
 // single-document request also takes the small single-document requests queued right behind
 // it (up to kPackDocs requests / kPackBytes bytes) and counts them in one per-document launch,
 // then splits the per-document tables into one resident table per request.
+//
+// Uploads. Each worker owns two pinned host buffers: it copies a request's text into one while
+// the other is on its way to the device, so host copies of several workers and their DMA
+// transfers overlap (a copy straight from pageable memory goes through the runtime's own
+// staging, one transfer at a time).
 #include <stdlib.h>
 #include <string.h>
 
@@ -37,6 +42,7 @@ constexpr uint32_t kPackDocs = 64;
 constexpr uint64_t kPackBytes = 4ull << 20;
 constexpr uint64_t kSmallBytes = 1ull << 20;
 constexpr uint64_t kPoolAlign = 256;
+constexpr uint64_t kStageBytes = 8ull << 20;  // per pinned upload buffer (two per worker)
 
 // First-fit allocator over [0, size) of the device pool.
 class Pool {
@@ -120,6 +126,13 @@ struct wc_server {
   std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
+  struct Staging {
+    uint8_t* buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool used[2] = {false, false};
+    uint32_t next = 0;
+  };
+  std::vector<Staging> staging;  // one per worker
   uint64_t next_id = 1;
   uint32_t holders = 0;  // requests holding count memory
   bool stop = false;
@@ -210,7 +223,27 @@ void finish(wc_server* S, Request* R, wc_status st) {
 
 // Count a group of requests. One request: its own wc_count (its opts). Several small
 // single-document requests: one per-document count, split per request.
-void run_group(wc_server* S, hipStream_t s, std::vector<std::shared_ptr<Request>>& G) {
+// Host text to device memory through the worker's two pinned buffers, in order on stream s.
+hipError_t upload(wc_server::Staging& W, uint8_t* dst, const uint8_t* src, uint64_t n,
+                  hipStream_t s) {
+  for (uint64_t off = 0; off < n; off += kStageBytes, W.next ^= 1) {
+    const uint32_t k = W.next;  // alternates across calls too: small texts overlap as well
+    const uint64_t m = std::min<uint64_t>(kStageBytes, n - off);
+    if (W.used[k]) {
+      hipError_t e = hipEventSynchronize(W.ev[k]);  // its previous transfer has finished
+      if (e != hipSuccess) return e;
+    }
+    memcpy(W.buf[k], src + off, m);
+    hipError_t e = hipMemcpyAsync(dst + off, W.buf[k], m, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(W.ev[k], s);
+    if (e != hipSuccess) return e;
+    W.used[k] = true;
+  }
+  return hipSuccess;
+}
+
+void run_group(wc_server* S, int idx, std::vector<std::shared_ptr<Request>>& G) {
+  hipStream_t s = S->streams[idx];
   const double t0 = now_s();
   for (auto& r : G) r->t_start = t0;
   if (G.size() == 1 && G[0]->merge) {
@@ -289,7 +322,7 @@ void run_group(wc_server* S, hipStream_t s, std::vector<std::shared_ptr<Request>
     hipError_t e = hipSuccess;
     for (auto& r : G) {
       if (r->dev_text) e = hipMemcpyAsync(d_text + pos, r->dev_text, r->len, hipMemcpyDeviceToDevice, s);
-      else if (r->len) e = hipMemcpyAsync(d_text + pos, r->text.data(), r->len, hipMemcpyHostToDevice, s);
+      else if (r->len) e = upload(S->staging[idx], d_text + pos, r->text.data(), r->len, s);
       if (e != hipSuccess) break;
       if (packed) {
         off.push_back(pos);
@@ -365,9 +398,20 @@ void run_group(wc_server* S, hipStream_t s, std::vector<std::shared_ptr<Request>
   for (auto& r : G) finish(S, r.get(), st);
 }
 
+void release_staging(wc_server* S) {
+  for (auto& W : S->staging) {
+    for (int k = 0; k < 2; ++k) {
+      if (W.ev[k]) hipEventSynchronize(W.ev[k]);
+      if (W.ev[k]) hipEventDestroy(W.ev[k]);
+      if (W.buf[k]) hipHostFree(W.buf[k]);
+      W.ev[k] = nullptr;
+      W.buf[k] = nullptr;
+    }
+  }
+}
+
 void worker(wc_server* S, int idx) {
   hipSetDevice(S->device);
-  hipStream_t s = S->streams[idx];
   while (true) {
     std::vector<std::shared_ptr<Request>> G;
     {
@@ -397,7 +441,7 @@ void worker(wc_server* S, int idx) {
         }
       }
     }
-    run_group(S, s, G);
+    run_group(S, idx, G);
   }
 }
 
@@ -426,6 +470,19 @@ wc_status wc_server_create(int device, uint64_t mem_budget, uint32_t max_streams
       return WC_EDEVICE;
     }
     S->streams.push_back(s);
+  }
+  S->staging.resize(max_streams);
+  for (auto& W : S->staging) {
+    for (int k = 0; k < 2; ++k) {
+      if (hipHostMalloc((void**)&W.buf[k], kStageBytes, hipHostMallocDefault) != hipSuccess ||
+          hipEventCreateWithFlags(&W.ev[k], hipEventDisableTiming) != hipSuccess) {
+        release_staging(S);
+        for (auto x : S->streams) hipStreamDestroy(x);
+        hipFree(S->pool_mem);
+        delete S;
+        return WC_EDEVICE;
+      }
+    }
   }
   for (uint32_t i = 0; i < max_streams; ++i) S->workers.emplace_back(worker, S, (int)i);
   *out = S;
@@ -548,6 +605,7 @@ wc_status wc_server_destroy(wc_server* S) {
   S->cv_work.notify_all();
   S->cv_mem.notify_all();
   for (auto& t : S->workers) t.join();
+  release_staging(S);
   for (auto s : S->streams) hipStreamDestroy(s);
   hipFree(S->pool_mem);
   delete S;
