@@ -61,9 +61,15 @@ typedef int32_t wc_status;
 /* debug flags (wc_opts.debug_flags) */
 #define WC_DEBUG_TIME   1u  /* time the count kernel with HIP events (wc_result.kernel_ms) */
 #define WC_DEBUG_NO_LDS 2u  /* skip the LDS table: every token goes to the global table */
-#define WC_DEBUG_DIRECT 4u  /* global mode: one-pass kernel (LDS table + global atomics) */
+#define WC_DEBUG_DIRECT 4u  /* global mode: one-pass kernel (LDS table + global atomics);
+                               per-document mode: the same kernel over one (document, word)
+                               table, sorted into the CSR afterwards */
 #define WC_DEBUG_SPILL  8u  /* global mode: two-pass kernels (LDS table + partitioned spill)
                                even for small inputs; by default they run from 256 MiB up */
+#define WC_DEBUG_DOCS   16u /* per-document mode: the document-centric kernel whatever the
+                               document sizes; by default it runs when documents average at
+                               most 64 KiB (larger ones leave too few documents per CU, since
+                               each document is counted by one workgroup), else as DIRECT */
 
 /* Launch tuning; a zero field takes the library default. */
 typedef struct wc_tuning {

@@ -18,6 +18,7 @@ constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultLds = 2048;
 constexpr uint32_t kDefaultBlock = 512;
 constexpr uint32_t kReduceLds = 5632;         // pass-2 LDS entries (110 KiB + 32 KiB of slots)
+constexpr uint64_t kDocKernelMaxMean = 64ull << 10;  // per-document mode: see use_doc_kernel
 constexpr uint64_t kSpillMinBytes = 256ull << 20;  // two-pass global count from this size
 constexpr uint64_t kMaxWgBytes = 1ull << 31;  // text per pass-1 workgroup (32-bit LDS counts)
 
@@ -163,8 +164,14 @@ struct DocLayout {
   uint64_t total;
 };
 
-bool use_doc_kernel(const wc_opts* o) {
-  return o->mode == WC_PER_DOC && !(o->debug_flags & WC_DEBUG_DIRECT);
+// The document-centric kernel counts each document in one workgroup: it wins with many small
+// documents and loses badly with a few large ones (a 1 MiB document keeps one workgroup busy
+// while the others idle), where the one-pass kernel over a (document, word) table spreads the
+// text over every CU.
+bool use_doc_kernel(const wc_opts* o, uint64_t len, uint64_t n_docs) {
+  if (o->mode != WC_PER_DOC || (o->debug_flags & WC_DEBUG_DIRECT)) return false;
+  if (o->debug_flags & WC_DEBUG_DOCS) return true;
+  return n_docs == 0 || len / n_docs <= kDocKernelMaxMean;
 }
 
 void layout_docs(uint64_t len, uint64_t n_docs, const wc_opts* o, void* ws, DocLayout* L) {
@@ -367,7 +374,7 @@ wc_status wc_count_plan(uint64_t corpus_len, uint64_t n_docs, const wc_opts* opt
   if (!resolve_tuning(opts->tuning, &tu)) return WC_EINVAL;
   global_stage(corpus_len, opts, &tu);
   if (opts->mode == WC_PER_DOC && n_docs >= 0xffffffffull) return WC_EINVAL;
-  if (use_doc_kernel(opts)) {
+  if (use_doc_kernel(opts, corpus_len, n_docs)) {
     if (corpus_len >= (1ull << 32)) return WC_EINVAL;  // packed output cursor: 32-bit fields
     DocLayout D;
     layout_docs(corpus_len, n_docs, opts, nullptr, &D);
@@ -399,7 +406,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
   if (per_doc && n_docs >= 0xffffffffull) return WC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(ensure_smem_attr());
-  if (use_doc_kernel(opts)) {
+  if (use_doc_kernel(opts, corpus_len, n_docs)) {
     if (corpus_len >= (1ull << 32)) return WC_EINVAL;
     DocLayout D;
     layout_docs(corpus_len, n_docs, opts, d_workspace, &D);
@@ -1096,6 +1103,7 @@ wc_status wc_autotune_plan(uint64_t len, uint64_t n_docs, const wc_opts* opts,
   for (const wc_tuning& t : tune_grid(opts)) {
     wc_opts o = *opts;
     o.tuning = &t;
+    if (o.mode == WC_PER_DOC) o.debug_flags |= WC_DEBUG_DOCS;  // the kernel the grid tunes
     wc_plan p;
     wc_status st = wc_count_plan(len, n_docs, &o, &p);
     if (st != WC_OK) return st;
@@ -1115,6 +1123,7 @@ wc_status wc_autotune(const uint8_t* d_sample, uint64_t len, const uint64_t* d_o
     wc_opts o = *opts;
     o.tuning = &t;
     o.debug_flags |= WC_DEBUG_TIME;
+    if (o.mode == WC_PER_DOC) o.debug_flags |= WC_DEBUG_DOCS;  // the kernel the grid tunes
     float ms = 0;
     wc_status st = WC_OK;
     for (int rep = 0; rep < 3 && st == WC_OK; ++rep) {  // first run warms up

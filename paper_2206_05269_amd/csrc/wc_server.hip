@@ -342,7 +342,7 @@ void run_group(wc_server* S, int idx, std::vector<std::shared_ptr<Request>>& G) 
     wc_result t;
     st = wc_count(d_text, total, d_off, n_docs_all, &o, ws, p.workspace_bytes, &t, s);
     S->launches++;
-    if (st == WC_ETABLEFULL && o.mode == WC_GLOBAL) {
+    if (st == WC_ETABLEFULL) {  // a global or (document, word) table: twice the slots
       o.table_slots = 2 * p.table_slots;
       pool_free(S, mem);
       continue;

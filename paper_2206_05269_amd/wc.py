@@ -22,7 +22,7 @@ WC_OK, WC_EINVAL, WC_ENOMEM, WC_ETABLEFULL, WC_EOVERFLOW, WC_EDEVICE, WC_EAGAIN 
     0, -1, -2, -3, -4, -5, -6
 WC_GLOBAL, WC_PER_DOC = 0, 1
 WC_FLUSH_ALL, WC_FLUSH_BYPASS = 0, 1
-WC_DEBUG_TIME, WC_DEBUG_NO_LDS, WC_DEBUG_DIRECT, WC_DEBUG_SPILL = 1, 2, 4, 8
+WC_DEBUG_TIME, WC_DEBUG_NO_LDS, WC_DEBUG_DIRECT, WC_DEBUG_SPILL, WC_DEBUG_DOCS = 1, 2, 4, 8, 16
 
 
 class WcError(RuntimeError):

@@ -221,7 +221,8 @@ def test_long_words(path):
     text = b" ".join([w1, w16, w17, w16.upper(), w17, w1.lower(), b"x", w1]) + b" "
     check(text, debug_flags=PATHS[path])
     check(text, [0, 1_000_001, len(text)], debug_flags=PATHS[path])
-    check(text, per_doc=True, offsets=[0, 1_000_001, len(text)])
+    check(text, per_doc=True, offsets=[0, 1_000_001, len(text)])  # large documents: one-pass
+    check(text, per_doc=True, offsets=[0, 1_000_001, len(text)], debug_flags=wc.WC_DEBUG_DOCS)
 
 
 @pytest.mark.parametrize("path", ["direct", "spill"])
@@ -291,12 +292,13 @@ def test_per_doc_relief_and_private_tables(lds):
     tu = wc.make_tuning(lds_entries=lds)
     c = synth.generate("plain-1MB")
     big = c.text.numpy()[:600_000]
-    check(big, [0, 10, 10, 250_000, 250_001, 600_000], per_doc=True, tuning=tu)
+    docs = wc.WC_DEBUG_DOCS  # the document-centric kernel, also for these large documents
+    check(big, [0, 10, 10, 250_000, 250_001, 600_000], per_doc=True, tuning=tu, debug_flags=docs)
     tiny = synth.random_text(120_000, 9, alphabet=b"abcAB '. ")
     off = np.arange(0, 120_001, 7)
     off[-1] = 120_000
-    check(tiny, off, per_doc=True, tuning=tu)
-    check(b"", [0, 0, 0], per_doc=True, tuning=tu)
+    check(tiny, off, per_doc=True, tuning=tu, debug_flags=docs)
+    check(b"", [0, 0, 0], per_doc=True, tuning=tu, debug_flags=docs)
 
 
 def test_per_doc_long_words_and_collisions():
@@ -306,6 +308,17 @@ def test_per_doc_long_words_and_collisions():
     for bits in (0, 3):
         check(text, off, per_doc=True, debug_hash_bits=bits)
         check(text, off, per_doc=True, debug_hash_bits=bits, tuning=wc.make_tuning(lds_entries=256))
+
+
+def test_per_doc_kernel_choice():
+    """By default the document-centric kernel runs for documents averaging at most 64 KiB and
+    the one-pass (document, word) table above that; both give the oracle's tables."""
+    c = synth.generate("plain-1MB")
+    text = c.text.numpy()[:800_000]
+    for off in ([0, 65_536, 131_072], [0, 65_537, 131_073], [0, 300_000, 300_000, 800_000]):
+        check(text[:off[-1]], off, per_doc=True)
+        check(text[:off[-1]], off, per_doc=True, debug_flags=wc.WC_DEBUG_DOCS)
+        check(text[:off[-1]], off, per_doc=True, debug_flags=wc.WC_DEBUG_DIRECT)
 
 
 def test_per_doc_direct_path_agrees():
