@@ -36,11 +36,14 @@ def measured_traffic():
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError, KeyError):
+        h = hashlib.sha256()
+        for src in rec["sources"]:  # the kernel's source file and the headers it includes
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
+    except (OSError, ValueError, KeyError, TypeError):
         return None
-    return int(rec["traffic_bytes"]) if sha == rec["source_sha256"] else None
+    return int(rec["traffic_bytes"]) if sha == rec["sources_sha256"] else None
 
 
 def cpu_baseline(corpus, sample_bytes: int):
