@@ -45,12 +45,13 @@ WC_DEV uint32_t doc_hash(uint64_t lo, uint64_t hi, uint32_t doc1) {
 
 // Count n occurrences of (doc1, word). Returns false when the table cannot take it (more
 // than `cap` live entries, or no slot within `max_probe` slots). Linear probing over groups of
-// 4 slots: one 32-byte read of a group's first words per step; the first empty slot ends the
-// search (no deletions while counting). Wave-uniform probe loop.
+// 4 slots: the words of a group's four slots are read together (each a 64-bit atomic read, so
+// a concurrent claim is never seen half written); the first empty slot ends the search (no
+// deletions while counting). Wave-uniform probe loop.
 WC_DEV bool doc_add(const DocTable& T, uint64_t lo, uint64_t hi, uint32_t doc1, uint32_t n,
                     uint32_t* live, uint32_t cap, uint32_t max_probe = 32) {
   const uint64_t hiw = hi | kTop;
-  const uint32_t ng = T.size >> 2;  // groups of 4 slots (T.lo is 16-byte aligned)
+  const uint32_t ng = T.size >> 2;  // groups of 4 slots (the size is a power of two >= 256)
   uint32_t g = __umulhi(doc_hash(lo, hi, doc1), ng);
   uint32_t probe = 0;
   bool active = true, ok = false;
@@ -58,11 +59,10 @@ WC_DEV bool doc_add(const DocTable& T, uint64_t lo, uint64_t hi, uint32_t doc1, 
     bool won = false;
     if (active) {
       const uint32_t b = g * 4;
-      const uint4 q0 = ((const uint4*)(T.lo + b))[0], q1 = ((const uint4*)(T.lo + b))[1];
-      const uint64_t v[4] = {(uint64_t)q0.x | ((uint64_t)q0.y << 32),
-                             (uint64_t)q0.z | ((uint64_t)q0.w << 32),
-                             (uint64_t)q1.x | ((uint64_t)q1.y << 32),
-                             (uint64_t)q1.z | ((uint64_t)q1.w << 32)};
+      uint64_t v[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j)  // four 64-bit atomic reads, issued together
+        v[j] = __hip_atomic_load(&T.lo[b + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       int state = 0;  // 0: all 4 taken by other words, 1: counted, 2: empty slot e, 3: look again
       uint32_t e = 0;
 #pragma unroll
