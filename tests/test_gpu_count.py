@@ -593,6 +593,22 @@ def test_server_alone_and_in_the_mix_are_identical():
     mix.close()
 
 
+def test_server_large_upload_and_packed_large_documents():
+    """A 20 MiB request crosses the worker's two 8 MiB pinned upload buffers three times; the
+    requests of a few hundred KB queued behind it are packed into one per-document launch whose
+    documents average above 64 KiB (the one-pass (document, word) table)."""
+    base = synth.generate("plain-1MB").text.numpy()
+    big = np.tile(base, 21)[:(20 << 20) + 12_345].tobytes()
+    mids = [base[a:a + n].tobytes() for a, n in ((0, 300_000), (100_000, 900_000),
+                                                  (5, 700_001), (333, 500_000))]
+    texts = [big] + mids
+    srv = wc.Server(mem_budget=1 << 30, max_streams=2)
+    ids = [srv.submit(t) for t in texts]
+    for t, i in zip(texts, ids):
+        assert wc.result_to_dict(srv.wait(i)) == oracle.count(t).as_dict()
+    srv.close()
+
+
 def test_server_budget_errors():
     srv = wc.Server(mem_budget=4 << 20, max_streams=1)
     with pytest.raises(wc.WcError) as e:
