@@ -72,6 +72,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-fold", action="store_true")
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--plain-docs", type=int, default=2000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -173,7 +174,44 @@ def main():
         out["batched"] = batched_docs_per_s(args.steps, args.warmup, args.plain_docs)
     if not args.no_serving:
         out["serving"] = serving(args.requests)
+    if not args.no_fold:
+        out["fold_sum"] = fold_sums(args.steps)
     print(json.dumps(out), flush=True)
+
+
+def fold_sums(steps: int):
+    """Section 4.2's float map-reduce at the paper's largest n (10^8): sum of sqrt(i) and the
+    alternating harmonic sum, binary64, no input in memory. Time per call from HIP events on
+    the call's stream; the paper's own times (V100, its Section 4.2 tables) are context only."""
+    import math
+    import torch
+    from paper_2206_05269_amd import wc
+    n = 10 ** 8
+    res = {"n": n, "dtype": "f64"}
+    paper_ms = {wc.WC_FOLD_SQRT: 73.372, wc.WC_FOLD_ALT_HARMONIC: 65.323}
+    for kind, name in ((wc.WC_FOLD_SQRT, "sqrt"), (wc.WC_FOLD_ALT_HARMONIC, "alt_harmonic")):
+        f = wc.FoldSum(kind, n)
+        for _ in range(2):
+            f.run(n)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            out = f.run(n)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        v = float(out.cpu().item())
+        if kind == wc.WC_FOLD_ALT_HARMONIC:
+            check = abs(v - math.log(2) - (-1) ** (n + 1) / (2 * n)) < 1e-11
+        else:
+            check = abs(v / (2 / 3 * n ** 1.5 + 0.5 * n ** 0.5 - 0.2078862249773546) - 1) < 1e-13
+        if not check:
+            log(f"MISMATCH fold {name}: {v}")
+            sys.exit(1)
+        res[name] = {"ms": round(ms, 4), "terms_per_s": round(n / (ms * 1e-3), 1), "sum": v,
+                     "paper_v100_ms": paper_ms[kind]}
+        log(f"fold {name}: n = {n} in {ms:.3f} ms ({n / ms / 1e6:.2f} Gterms/s), sum {v!r}")
+    return res
 
 
 def serving(n_requests: int):

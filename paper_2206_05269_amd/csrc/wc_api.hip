@@ -1146,3 +1146,8 @@ wc_status wc_autotune(const uint8_t* d_sample, uint64_t len, const uint64_t* d_o
 }
 
 }  // extern "C"
+
+namespace wc {
+// the calling thread's last HIP error, for entry points defined in other files
+void set_last_hip(int32_t e) { g_last_hip = e; }
+}  // namespace wc

@@ -23,6 +23,7 @@ WC_OK, WC_EINVAL, WC_ENOMEM, WC_ETABLEFULL, WC_EOVERFLOW, WC_EDEVICE, WC_EAGAIN 
 WC_GLOBAL, WC_PER_DOC = 0, 1
 WC_FLUSH_ALL, WC_FLUSH_BYPASS = 0, 1
 WC_DEBUG_TIME, WC_DEBUG_NO_LDS, WC_DEBUG_DIRECT, WC_DEBUG_SPILL, WC_DEBUG_DOCS = 1, 2, 4, 8, 16
+WC_FOLD_SQRT, WC_FOLD_ALT_HARMONIC = 0, 1
 
 
 class WcError(RuntimeError):
@@ -122,6 +123,10 @@ def lib():
                                   ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float), vp]
         L.wc_autotune_plan.restype = ctypes.c_int32
         L.wc_autotune.restype = ctypes.c_int32
+        L.wc_fold_sum_plan.argtypes = [u64, ctypes.POINTER(u64)]
+        L.wc_fold_sum.argtypes = [u32, u64, vp, vp, u64, vp]
+        L.wc_fold_sum_plan.restype = ctypes.c_int32
+        L.wc_fold_sum.restype = ctypes.c_int32
         L.wc_batch_plan.argtypes = [ctypes.POINTER(Opts), u64, u64, ctypes.POINTER(u64)]
         L.wc_batch_create.argtypes = [ctypes.POINTER(Opts), u64, u64, vp, u64,
                                       ctypes.POINTER(vp)]
@@ -396,6 +401,40 @@ def hash_words(words: Sequence[bytes], device="cuda") -> list:
     if st != WC_OK:
         raise WcError(st, "wc_hash_words")
     return [int(x) & 0xFFFFFFFFFFFFFFFF for x in d_out[:len(words)].cpu().tolist()]
+
+
+class FoldSum:
+    """Section 4.2's float map-reduce (wc_fold_sum) with its workspace and output held on the
+    device, for repeated calls: run(n) enqueues the sum of terms 1..n on the stream and returns
+    the one-element float64 device tensor it writes."""
+
+    def __init__(self, kind: int, max_n: int, device="cuda"):
+        need = ctypes.c_uint64()
+        st = lib().wc_fold_sum_plan(max_n, ctypes.byref(need))
+        if st != WC_OK:
+            raise WcError(st, "wc_fold_sum_plan")
+        self.kind = kind
+        self.max_n = max_n
+        self.workspace = _alloc(need.value, device)
+        self.out = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def run(self, n: int, stream=None) -> torch.Tensor:
+        if n > self.max_n:
+            raise ValueError("n above max_n")
+        st = lib().wc_fold_sum(self.kind, n, ctypes.c_void_p(self.out.data_ptr()),
+                               ctypes.c_void_p(self.workspace.data_ptr()),
+                               self.workspace.numel(), _stream_handle(stream))
+        if st != WC_OK:
+            raise WcError(st, "wc_fold_sum")
+        return self.out
+
+
+def fold_sum(kind: int, n: int, device="cuda") -> float:
+    """Sum over i = 1..n of sqrt(i) (WC_FOLD_SQRT) or (-1)^(i+1)/i (WC_FOLD_ALT_HARMONIC)."""
+    f = FoldSum(kind, n, device)
+    out = f.run(n)
+    torch.cuda.current_stream().synchronize()
+    return float(out.cpu().item())
 
 
 def output_sizes(corpus: torch.Tensor, offsets: torch.Tensor, *, per_doc: bool = True,

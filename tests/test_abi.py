@@ -1,4 +1,4 @@
-"""The C ABI without a GPU: libwc.so loads, exports every function include/wc.h declares, and
+"""The C ABI without a GPU: libwc.so loads, exports every function include/*.h declares, and
 the ctypes structures of the binding have the C layout (checked with a small gcc program)."""
 import ctypes
 import os
@@ -10,11 +10,12 @@ import pytest
 from paper_2206_05269_amd import wc
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "wc.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*[\w\s\*]+?\b(wc_\w+)\s*\(", src, flags=re.M)))
 
@@ -22,7 +23,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     f = declared_functions()
     for name in ("wc_count", "wc_count_plan", "wc_merge", "wc_merge_plan", "wc_topk_ratio",
-                 "wc_topk_ratio_plan", "wc_strerror", "wc_last_hip_error", "wc_hash_words"):
+                 "wc_topk_ratio_plan", "wc_strerror", "wc_last_hip_error", "wc_hash_words",
+                 "wc_fold_sum", "wc_fold_sum_plan"):
         assert name in f
 
 
@@ -65,3 +67,16 @@ def test_struct_layouts_match_c(tmp_path):
             wc.Result.d_word_offsets.offset, wc.Result.kernel_ms.offset,
             wc.TopKStruct.n_rows.offset]
     assert got == want
+
+
+def test_fold_sum_argument_errors_without_gpu():
+    """Rejected before any device work: unknown kind, n above 2^53, small or missing workspace."""
+    L = wc.lib()
+    need = ctypes.c_uint64()
+    assert L.wc_fold_sum_plan(10 ** 8, ctypes.byref(need)) == 0 and need.value == 2048 * 8
+    assert L.wc_fold_sum_plan(1, ctypes.byref(need)) == 0 and need.value == 8
+    p = ctypes.c_void_p(4096)  # never dereferenced: every call below fails its checks first
+    assert L.wc_fold_sum(2, 10, p, p, 1 << 20, None) == wc.WC_EINVAL
+    assert L.wc_fold_sum(0, (1 << 53) + 1, p, p, 1 << 20, None) == wc.WC_EINVAL
+    assert L.wc_fold_sum(0, 10 ** 8, p, p, 8, None) == wc.WC_EINVAL
+    assert L.wc_fold_sum(0, 10, None, p, 1 << 20, None) == wc.WC_EINVAL
