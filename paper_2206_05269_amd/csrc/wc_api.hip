@@ -227,7 +227,11 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
   const bool per_doc = o->mode == WC_PER_DOC;
   uint64_t S = o->table_slots;
   if (!S) {
-    uint64_t want = per_doc ? len / 8 : len / 32;
+    // one slot per 16 bytes of text: short texts have many distinct words per byte (Zipf 1.05
+    // text over 500,000 words has one distinct word per 16 bytes at 32 KiB, per 22 at 256 KiB,
+    // per 30 at 1 MiB), and a table that overflows costs a whole second count; long texts hit
+    // the cap below
+    uint64_t want = per_doc ? len / 8 : len / 16;
     want = std::max<uint64_t>(want, 4096);
     want = std::min<uint64_t>(want, per_doc ? (1ull << 28) : (1ull << 22));
     S = next_pow2(want);

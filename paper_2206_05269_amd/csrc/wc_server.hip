@@ -131,10 +131,13 @@ struct wc_server {
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool used[2] = {false, false};
     uint32_t next = 0;
+    uint64_t* small = nullptr;  // pinned: a few values read back from the device
+    unsigned long long* d_small = nullptr;  // device: per-request token totals of a group
   };
   std::vector<Staging> staging;  // one per worker
   uint64_t next_id = 1;
   uint32_t holders = 0;  // requests holding count memory
+  uint32_t resident_waiters = 0;  // holders waiting in keep_resident for resident memory
   bool stop = false;
   std::atomic<uint64_t> launches{0};
 };
@@ -142,30 +145,66 @@ struct wc_server {
 namespace {
 
 // compact a table (device arrays) into one resident block: [word_offsets | counts | words]
-wc_status keep_resident(wc_server* S, hipStream_t s, const wc_result& t, uint64_t e_begin,
-                        uint64_t n, Request* R) {
+// d[i] = s[i] - s[0] for i < n1: a table's word offsets rebased to its first word
+__global__ void rebase_offsets_kernel(const uint64_t* src, uint64_t n1, uint64_t* dst) {
+  const uint64_t b0 = src[0];
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n1;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i] - b0;
+}
+
+// *out += sum of n counts (4 or 8 bytes each); integer, so the order of additions is free
+__global__ void sum_counts_kernel(const void* counts, uint32_t cb, uint64_t n,
+                                  unsigned long long* out) {
+  unsigned long long v = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    v += cb == 4 ? (unsigned long long)((const int32_t*)counts)[i]
+                 : (unsigned long long)((const int64_t*)counts)[i];
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
+
+uint32_t small_grid(uint64_t n) {
+  const uint64_t g = (n + 255) / 256;
+  return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(g, 1), 1024);
+}
+
+// Copy entries [e_begin, e_begin + n) of table t into an exact-size resident block. Only the
+// byte range of their words crosses to the host (two values); offsets are rebased and counts
+// and words copied on the device.
+wc_status keep_resident(wc_server* S, wc_server::Staging& W, hipStream_t s, const wc_result& t,
+                        uint64_t e_begin, uint64_t n, Request* R) {
   const uint32_t cb = t.count_bytes;
-  // word offsets of the kept entries (absolute in t) and their byte range
-  std::vector<uint64_t> woff(n + 1);
-  if (hipMemcpyAsync(woff.data(), t.d_word_offsets + e_begin, (n + 1) * 8,
-                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(&W.small[0], t.d_word_offsets + e_begin, 8, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(&W.small[1], t.d_word_offsets + e_begin + n, 8, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return WC_EDEVICE;
-  const uint64_t b0 = woff[0], nb = woff[n] - woff[0];
-  for (auto& x : woff) x -= b0;
+  const uint64_t b0 = W.small[0], nb = W.small[1] - W.small[0];
   const uint64_t bytes = (n + 1) * 8 + n * cb + nb + 64;
   uint8_t* mem;
   {
-    // never wait here (this worker still holds its count memory): a budget that resident
-    // tables have filled is reported as WC_ENOMEM for this request
-    std::lock_guard<std::mutex> lk(S->mu);
+    // This worker holds count memory. It waits only while another holder that is not itself
+    // waiting here can still return memory; otherwise (resident tables fill the budget) the
+    // request fails with WC_ENOMEM, so two workers never wait on each other.
+    std::unique_lock<std::mutex> lk(S->mu);
     mem = S->pool.alloc(bytes);
+    while (!mem && !S->stop && S->holders > S->resident_waiters + 1) {
+      ++S->resident_waiters;
+      S->cv_mem.wait(lk);
+      --S->resident_waiters;
+      mem = S->pool.alloc(bytes);
+    }
   }
   if (!mem) return WC_ENOMEM;
   uint64_t* d_off = (uint64_t*)mem;
   uint8_t* d_cnt = mem + (((n + 1) * 8 + 15) & ~15ull);
   uint8_t* d_words = d_cnt + ((n * cb + 15) & ~15ull);
-  hipError_t e = hipMemcpyAsync(d_off, woff.data(), (n + 1) * 8, hipMemcpyHostToDevice, s);
+  hipLaunchKernelGGL(rebase_offsets_kernel, dim3(small_grid(n + 1)), dim3(256), 0, s,
+                     (const uint64_t*)(t.d_word_offsets + e_begin), n + 1, d_off);
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess && n)
     e = hipMemcpyAsync(d_cnt, (const uint8_t*)t.d_counts + e_begin * cb, n * cb,
                        hipMemcpyDeviceToDevice, s);
@@ -279,7 +318,7 @@ void run_group(wc_server* S, int idx, std::vector<std::shared_ptr<Request>>& G) 
     wc_result t;
     st = wc_merge(ins.data(), (uint32_t)ins.size(), &o, ws, p.workspace_bytes, &t, s);
     S->launches++;
-    if (st == WC_OK) st = keep_resident(S, s, t, 0, t.n_entries, R);
+    if (st == WC_OK) st = keep_resident(S, S->staging[idx], s, t, 0, t.n_entries, R);
     if (st == WC_OK) R->res.total_tokens = t.total_tokens;
     pool_free(S, ws);
     return finish(S, R, st);
@@ -359,7 +398,7 @@ void run_group(wc_server* S, int idx, std::vector<std::shared_ptr<Request>>& G) 
     }
     if (st == WC_OK) {
       if (!packed) {
-        st = keep_resident(S, s, t, 0, t.n_entries, G[0].get());
+        st = keep_resident(S, S->staging[idx], s, t, 0, t.n_entries, G[0].get());
         if (st == WC_OK) G[0]->res.total_tokens = t.total_tokens;
       } else {
         std::vector<uint64_t> dptr(n_docs_all), dlen(n_docs_all);
@@ -369,26 +408,26 @@ void run_group(wc_server* S, int idx, std::vector<std::shared_ptr<Request>>& G) 
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = WC_EDEVICE;
         for (size_t i = 0; st == WC_OK && i < G.size(); ++i) {
-          wc_status si = keep_resident(S, s, t, dptr[i], dlen[i], G[i].get());
+          wc_status si = keep_resident(S, S->staging[idx], s, t, dptr[i], dlen[i], G[i].get());
           if (si != WC_OK) st = si;
         }
-        // token totals per request: sum of its counts (host side, from the resident table)
-        for (size_t i = 0; st == WC_OK && i < G.size(); ++i) {
-          Request* R = G[i].get();
-          uint64_t n = R->res.n_entries, sum = 0;
-          if (n) {
-            std::vector<int64_t> c8(n);
-            std::vector<int32_t> c4(n);
-            if (R->res.count_bytes == 4) {
-              e = hipMemcpyAsync(c4.data(), R->res.d_counts, n * 4, hipMemcpyDeviceToHost, s);
-            } else {
-              e = hipMemcpyAsync(c8.data(), R->res.d_counts, n * 8, hipMemcpyDeviceToHost, s);
-            }
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) { st = WC_EDEVICE; break; }
-            for (uint64_t j = 0; j < n; ++j) sum += R->res.count_bytes == 4 ? (uint64_t)c4[j] : (uint64_t)c8[j];
+        // token totals per request: sum of its counts, on the device, read back together
+        wc_server::Staging& W = S->staging[idx];
+        if (st == WC_OK) {
+          e = hipMemsetAsync(W.d_small, 0, G.size() * 8, s);
+          for (size_t i = 0; e == hipSuccess && i < G.size(); ++i) {
+            const Request* R = G[i].get();
+            if (!R->res.n_entries) continue;
+            hipLaunchKernelGGL(sum_counts_kernel, dim3(small_grid(R->res.n_entries)), dim3(256), 0,
+                               s, R->res.d_counts, R->res.count_bytes, R->res.n_entries,
+                               W.d_small + i);
+            e = hipGetLastError();
           }
-          R->res.total_tokens = sum;
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(W.small, W.d_small, G.size() * 8, hipMemcpyDeviceToHost, s);
+          if (e == hipSuccess) e = hipStreamSynchronize(s);
+          if (e != hipSuccess) st = WC_EDEVICE;
+          for (size_t i = 0; st == WC_OK && i < G.size(); ++i) G[i]->res.total_tokens = W.small[i];
         }
       }
     }
@@ -401,12 +440,16 @@ void run_group(wc_server* S, int idx, std::vector<std::shared_ptr<Request>>& G) 
 void release_staging(wc_server* S) {
   for (auto& W : S->staging) {
     for (int k = 0; k < 2; ++k) {
-      if (W.ev[k]) hipEventSynchronize(W.ev[k]);
-      if (W.ev[k]) hipEventDestroy(W.ev[k]);
-      if (W.buf[k]) hipHostFree(W.buf[k]);
+      if (W.ev[k]) (void)hipEventSynchronize(W.ev[k]);
+      if (W.ev[k]) (void)hipEventDestroy(W.ev[k]);
+      if (W.buf[k]) (void)hipHostFree(W.buf[k]);
       W.ev[k] = nullptr;
       W.buf[k] = nullptr;
     }
+    if (W.small) (void)hipHostFree(W.small);
+    if (W.d_small) (void)hipFree(W.d_small);
+    W.small = nullptr;
+    W.d_small = nullptr;
   }
 }
 
@@ -475,7 +518,10 @@ wc_status wc_server_create(int device, uint64_t mem_budget, uint32_t max_streams
   for (auto& W : S->staging) {
     for (int k = 0; k < 2; ++k) {
       if (hipHostMalloc((void**)&W.buf[k], kStageBytes, hipHostMallocDefault) != hipSuccess ||
-          hipEventCreateWithFlags(&W.ev[k], hipEventDisableTiming) != hipSuccess) {
+          hipEventCreateWithFlags(&W.ev[k], hipEventDisableTiming) != hipSuccess ||
+          (k == 0 && (hipHostMalloc((void**)&W.small, kPackDocs * 8, hipHostMallocDefault) !=
+                          hipSuccess ||
+                      hipMalloc((void**)&W.d_small, kPackDocs * 8) != hipSuccess))) {
         release_staging(S);
         for (auto x : S->streams) hipStreamDestroy(x);
         hipFree(S->pool_mem);
