@@ -341,6 +341,13 @@ void run_group(wc_server* S, int idx, std::vector<std::shared_ptr<Request>>& G) 
     wc_plan p;
     st = wc_count_plan(total, n_docs_all, &o, &p);
     if (st != WC_OK) break;
+    if (packed && !(o.debug_flags & WC_DEBUG_DOCS) && p.workspace_bytes > S->budget / 4) {
+      // the one-pass (document, word) table needs about 12 bytes per text byte; under a
+      // tight budget the document-centric kernel (a fraction of that) is counted instead
+      o.debug_flags |= WC_DEBUG_DOCS;
+      st = wc_count_plan(total, n_docs_all, &o, &p);
+      if (st != WC_OK) break;
+    }
     const uint64_t off_bytes = (n_docs_all + 1) * 8;
     const uint64_t need = p.workspace_bytes + ((total + 255) & ~255ull) + off_bytes + 512;
     if (need > S->budget) {
