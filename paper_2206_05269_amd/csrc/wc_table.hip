@@ -63,10 +63,12 @@ WC_DEV uint64_t block_excl_scan(uint64_t v, uint64_t* s_tmp, uint64_t* total) {
 __global__ __launch_bounds__(kExportBlock) void export_count_kernel(ExportParams E) {
   __shared__ uint64_t s_a[kExportBlock / 64], s_b[kExportBlock / 64];
   const uint64_t b = blockIdx.x;
-  const uint64_t first = b * kExportSpan + (uint64_t)threadIdx.x * kExportItems;
+  // only the block's totals are needed here, so slots are read wave-contiguously (consecutive
+  // lanes, consecutive slots) rather than in the write kernel's per-thread runs
+  const uint64_t first = b * kExportSpan + threadIdx.x;
   uint64_t n = 0, bytes = 0;
   for (uint32_t j = 0; j < kExportItems; ++j) {
-    uint64_t i = first + j;
+    uint64_t i = first + (uint64_t)j * kExportBlock;
     if (i < E.slots) {
       Slot sl = E.table[i];
       if (sl.key) {
