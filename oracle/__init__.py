@@ -25,6 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wc_oracle.cpp")
+_PAR = os.path.join(_HERE, "cpu_parallel.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -33,11 +34,12 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 
 def build(force: bool = True, sanitize: bool = False, out: str | None = None) -> str:
-    """Compile the oracle with g++ (-O2, single-threaded)."""
+    """Compile the oracle (single-threaded) and the paper's threaded CPU design (a timed
+    baseline, cpu_parallel.cpp) with g++ -O2."""
     out = out or _LIB
     if not force and os.path.exists(out):
         return out
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", out, _SRC]
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", out, _SRC, _PAR]
     if sanitize:
         cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-g"]
     subprocess.run(cmd, check=True)
@@ -55,6 +57,9 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.oracle_count.restype = ctypes.c_void_p
         L.oracle_count.argtypes = [_u8p, ctypes.c_uint64, _u64p, ctypes.c_uint64, ctypes.c_int]
+        L.oracle_count_utf8.restype = ctypes.c_void_p
+        L.oracle_count_utf8.argtypes = [_u8p, ctypes.c_uint64, _u64p, ctypes.c_uint64,
+                                        ctypes.c_int]
         L.oracle_merge.restype = ctypes.c_void_p
         L.oracle_merge.argtypes = [ctypes.c_uint32, ctypes.POINTER(_u8p), ctypes.POINTER(_u64p),
                                    ctypes.POINTER(_u64p), _u64p]
@@ -70,6 +75,18 @@ def lib():
                                         ctypes.POINTER(_u64p), ctypes.POINTER(_u64p), _u64p,
                                         ctypes.c_uint32, ctypes.c_uint64, _u64p, _u64p, _u64p,
                                         _dp, _u64p, _u64p, _u8p]
+        L.cpu_parallel_count.restype = ctypes.c_void_p
+        L.cpu_parallel_count.argtypes = [_u8p, ctypes.c_uint64, _u64p, ctypes.c_uint64,
+                                         ctypes.c_uint32]
+        for f in ("cpu_parallel_size", "cpu_parallel_total", "cpu_parallel_word_bytes"):
+            getattr(L, f).restype = ctypes.c_uint64
+            getattr(L, f).argtypes = [ctypes.c_void_p]
+        L.cpu_parallel_seconds.restype = ctypes.c_double
+        L.cpu_parallel_seconds.argtypes = [ctypes.c_void_p]
+        L.cpu_parallel_export.restype = None
+        L.cpu_parallel_export.argtypes = [ctypes.c_void_p, _u8p, _u64p, _u64p]
+        L.cpu_parallel_free.restype = None
+        L.cpu_parallel_free.argtypes = [ctypes.c_void_p]
         L.oracle_joint_word_bytes.restype = ctypes.c_uint64
         L.oracle_joint_word_bytes.argtypes = [ctypes.c_uint32, ctypes.POINTER(_u8p),
                                               ctypes.POINTER(_u64p), _u64p]
@@ -126,8 +143,9 @@ class OracleError(ValueError):
     pass
 
 
-def count(text, offsets=None, per_doc: bool = False) -> Table:
-    """Count words of text (bytes / uint8 array) split into documents by offsets."""
+def count(text, offsets=None, per_doc: bool = False, utf8: bool = False) -> Table:
+    """Count words of text (bytes / uint8 array) split into documents by offsets. utf8: the
+    UTF-8 reading of wc_oracle.cpp (multi-byte word characters, ASCII-only folding)."""
     buf = np.frombuffer(bytes(text), dtype=np.uint8) if isinstance(text, (bytes, bytearray)) \
         else np.ascontiguousarray(text, dtype=np.uint8)
     if offsets is None:
@@ -137,7 +155,8 @@ def count(text, offsets=None, per_doc: bool = False) -> Table:
     if n_docs < 0:
         raise OracleError("offsets must hold at least one value")
     keep = buf if len(buf) else np.zeros(1, dtype=np.uint8)
-    h = lib().oracle_count(_p(keep, _u8p), len(buf), _p(off, _u64p), n_docs, int(per_doc))
+    fn = lib().oracle_count_utf8 if utf8 else lib().oracle_count
+    h = fn(_p(keep, _u8p), len(buf), _p(off, _u64p), n_docs, int(per_doc))
     if not h:
         raise OracleError("invalid document offsets")
     return _export(h, per_doc)
@@ -213,3 +232,29 @@ def topk_ratio(tables, k: int, min_count: int = 1) -> TopK:
         nrs.append(onr[t * kk:t * kk + r].copy())
         scs.append(osc[t * kk:t * kk + r].copy())
     return TopK(words, ncs, nrs, scs, int(V))
+
+
+def cpu_parallel(text, offsets=None, threads: int = 1):
+    """The paper's CPU design (Section 3.1 threads each counting a share of the text, Section 3.2
+    merging their dictionaries), for timing beside the GPU counter: (dict {word: count}, total
+    tokens, seconds spent counting and merging)."""
+    buf = np.frombuffer(bytes(text), dtype=np.uint8) if isinstance(text, (bytes, bytearray)) \
+        else np.ascontiguousarray(text, dtype=np.uint8)
+    if offsets is None:
+        offsets = [0, len(buf)]
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    keep = buf if len(buf) else np.zeros(1, dtype=np.uint8)
+    L = lib()
+    h = L.cpu_parallel_count(_p(keep, _u8p), len(buf), _p(off, _u64p), len(off) - 1, threads)
+    try:
+        n = L.cpu_parallel_size(h)
+        wb = L.cpu_parallel_word_bytes(h)
+        words = np.zeros(max(wb, 1), dtype=np.uint8)
+        offs = np.zeros(n + 1, dtype=np.uint64)
+        cnts = np.zeros(max(n, 1), dtype=np.uint64)
+        L.cpu_parallel_export(h, _p(words, _u8p), _p(offs, _u64p), _p(cnts, _u64p))
+        wbytes = words.tobytes()
+        d = {wbytes[offs[e]:offs[e + 1]]: int(cnts[e]) for e in range(n)}
+        return d, int(L.cpu_parallel_total(h)), float(L.cpu_parallel_seconds(h))
+    finally:
+        L.cpu_parallel_free(h)

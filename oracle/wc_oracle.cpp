@@ -71,6 +71,60 @@ Table from_maps(std::vector<std::unordered_map<std::string, uint64_t>>& maps, ui
   return t;
 }
 
+// ---- UTF-8 mode (the "other languages" of Section 5.2) ---------------------------------------
+// Reading used: a document is decoded as UTF-8 (the well-formed byte sequences of the Unicode
+// Standard, Table 3-7); a byte that does not belong to a well-formed sequence inside the
+// document is a delimiter. A code point below U+0080 is classified as in ASCII mode; a
+// higher one is a word character unless it is in U+0080..U+00BF (Latin-1 controls,
+// punctuation and symbols), U+00D7, U+00F7, U+2000..U+206F (general punctuation),
+// U+3000..U+303F (CJK symbols and punctuation) or U+FEFF. Folding stays ASCII-only; the
+// word is the folded run of bytes.
+bool is_word_cp(uint32_t cp) {
+  if (cp < 0x80) return is_word_byte((uint8_t)cp);
+  if (cp <= 0xBF || cp == 0xD7 || cp == 0xF7 || cp == 0xFEFF) return false;
+  if (cp >= 0x2000 && cp <= 0x206F) return false;
+  if (cp >= 0x3000 && cp <= 0x303F) return false;
+  return true;
+}
+
+// Length (1..4) and code point of the well-formed sequence starting at t[i] within [i, end),
+// or 0 when the byte at i does not start one.
+int utf8_seq(const uint8_t* t, uint64_t i, uint64_t end, uint32_t* cp) {
+  const uint8_t b = t[i];
+  if (b < 0x80) {
+    *cp = b;
+    return 1;
+  }
+  int n;
+  uint8_t lo = 0x80, hi = 0xBF;  // allowed range of the second byte
+  uint32_t v;
+  if (b >= 0xC2 && b <= 0xDF) {
+    n = 2;
+    v = b & 0x1F;
+  } else if (b >= 0xE0 && b <= 0xEF) {
+    n = 3;
+    v = b & 0x0F;
+    if (b == 0xE0) lo = 0xA0;
+    if (b == 0xED) hi = 0x9F;
+  } else if (b >= 0xF0 && b <= 0xF4) {
+    n = 4;
+    v = b & 0x07;
+    if (b == 0xF0) lo = 0x90;
+    if (b == 0xF4) hi = 0x8F;
+  } else {
+    return 0;
+  }
+  if (i + n > end) return 0;
+  for (int k = 1; k < n; ++k) {
+    const uint8_t c = t[i + k];
+    const uint8_t l = k == 1 ? lo : 0x80, h = k == 1 ? hi : 0xBF;
+    if (c < l || c > h) return 0;
+    v = (v << 6) | (c & 0x3F);
+  }
+  *cp = v;
+  return n;
+}
+
 bool offsets_valid(uint64_t len, const uint64_t* off, uint64_t n_docs) {
   if (n_docs > 0 && off == nullptr) return false;
   if (n_docs == 0) return true;
@@ -98,6 +152,43 @@ void* oracle_count(const uint8_t* text, uint64_t len, const uint64_t* offsets, u
       if (!is_word_byte(text[i])) { ++i; continue; }
       std::string w;
       while (i < end && is_word_byte(text[i])) w.push_back(char(fold(text[i++])));
+      m[w] += 1;
+      ++total;
+    }
+  }
+  return new Table(from_maps(maps, total));
+}
+
+// Count words as oracle_count, with the UTF-8 reading above: each document is decoded, the
+// bytes of its word code points are word bytes, every other byte a delimiter.
+void* oracle_count_utf8(const uint8_t* text, uint64_t len, const uint64_t* offsets,
+                        uint64_t n_docs, int per_doc) {
+  if (!offsets_valid(len, offsets, n_docs)) return nullptr;
+  std::vector<std::unordered_map<std::string, uint64_t>> maps(per_doc ? n_docs : 1);
+  uint64_t total = 0;
+  std::vector<uint8_t> word;
+  for (uint64_t d = 0; d < n_docs; ++d) {
+    auto& m = maps[per_doc ? d : 0];
+    const uint64_t a = offsets[d], end = offsets[d + 1];
+    word.assign(end - a, 0);
+    for (uint64_t i = a; i < end;) {
+      uint32_t cp = 0;
+      const int n = utf8_seq(text, i, end, &cp);
+      if (n == 0) {  // not part of a well-formed sequence: a delimiter
+        ++i;
+        continue;
+      }
+      const uint8_t wb = is_word_cp(cp) ? 1 : 0;
+      for (int k = 0; k < n; ++k) word[i - a + k] = wb;
+      i += n;
+    }
+    for (uint64_t i = a; i < end;) {
+      if (!word[i - a]) {
+        ++i;
+        continue;
+      }
+      std::string w;
+      while (i < end && word[i - a]) w.push_back(char(fold(text[i++])));
       m[w] += 1;
       ++total;
     }

@@ -338,3 +338,100 @@ def test_topk_generated_corpora():
     cs = synth.generate("corpora-4x2000", scale=0.05)
     dicts = [oracle.count(c.text.numpy(), c.offsets.numpy()).as_dict() for c in cs]
     _check_topk(dicts, 50)
+
+
+# ------------------------------------------------------------------------------------------
+# the paper's threaded CPU design (a timed baseline): same tables as the oracle
+# ------------------------------------------------------------------------------------------
+
+def test_cpu_parallel_matches_oracle():
+    """Byte ranges split inside words and documents; every thread count gives the oracle's
+    table (the ownership rule: a token belongs to the range of its first byte)."""
+    text = synth.random_text(200_000, 21, alphabet=b"aAzZ09' ,.\x80\n-bcY")
+    for n_docs in (1, 7, 300):
+        off = synth.random_splits(len(text), n_docs, n_docs)
+        want = oracle.count(text, off)
+        for threads in (1, 2, 3, 8, 33):
+            got, total, _ = oracle.cpu_parallel(text, off, threads)
+            assert total == want.total
+            assert got == want.as_dict()
+    d, total, _ = oracle.cpu_parallel(b"", [0, 0], 4)
+    assert d == {} and total == 0
+    c = synth.generate("plain-1MB")
+    d, total, _ = oracle.cpu_parallel(c.text.numpy(), c.offsets.numpy(), 8)
+    assert d == c.expected_table() and total == c.n_tokens
+
+
+# ------------------------------------------------------------------------------------------
+# UTF-8 mode (Section 5.2's other languages): the oracle's reading against Python's own UTF-8
+# decoder and regular expressions
+# ------------------------------------------------------------------------------------------
+
+ASCII_FOLD = {c: c + 32 for c in range(ord("A"), ord("Z") + 1)}
+# word characters of the UTF-8 reading: [a-z0-9'] and every code point from U+0080 up except
+# U+0080-U+00BF, U+00D7, U+00F7, U+2000-U+206F, U+3000-U+303F and U+FEFF; the surrogate block
+# is left out too (Python's surrogateescape decodes each byte outside a well-formed sequence to
+# one of them, so such bytes are delimiters)
+UTF8_WORD = re.compile("[a-z0-9'\u00c0-\u00d6\u00d8-\u00f6\u00f8-\u1fff\u2070-\u2fff"
+                       "\u3040-\ud7ff\ue000-\ufefe\uff00-\U0010ffff]+")
+
+
+def re_count_utf8(docs):
+    c = collections.Counter()
+    for d in docs:
+        s = d.decode("utf-8", "surrogateescape").translate(ASCII_FOLD)
+        for w in UTF8_WORD.findall(s):
+            c[w.encode("utf-8")] += 1
+    return dict(c)
+
+
+def _join(docs):
+    text = b"".join(docs)
+    off = np.zeros(len(docs) + 1, dtype=np.int64)
+    np.cumsum([len(d) for d in docs], out=off[1:])
+    return text, off
+
+
+UTF8_ALPHABET = [b"a", b"Z", b" ", b"\xc3", b"\xa9", b"\xe2", b"\x80", b"\x94", b"\xf0",
+                 b"\x9f", b"\xed", b"\xa0"]
+
+
+def test_utf8_every_short_string_against_python_decoder():
+    """Every string of up to 4 bytes over leads, continuations and ASCII (one document each):
+    well-formed letters (é, 4-byte code points), em dash (general punctuation), overlong,
+    surrogate and truncated sequences, stray continuation bytes."""
+    docs = [b"".join(p) for n in range(0, 5) for p in itertools.product(UTF8_ALPHABET, repeat=n)]
+    text, off = _join(docs)
+    got = oracle.count(text, off, utf8=True).as_dict()
+    assert got == re_count_utf8(docs)
+    per = oracle.count(text, off, per_doc=True, utf8=True).as_dict()
+    for d in (0, 5, 100, 2000, len(docs) - 1):
+        assert {w: n for (dd, w), n in per.items() if dd == d} == re_count_utf8([docs[d]])
+
+
+def test_utf8_random_bytes_and_document_cuts():
+    """Random bytes (mostly non-ASCII) with random document cuts, which split sequences: a
+    sequence cut by a document end is ill-formed in both documents."""
+    rng = random.Random(7)
+    for seed in range(6):
+        n = 20_000
+        raw = bytes(rng.choice(b"ab \xc3\xa9\xe2\x80\x94\xe6\x97\xa5\xf0\x9f\x98\x80\xce\xa9.")
+                    for _ in range(n))
+        cuts = sorted(rng.randrange(0, n + 1) for _ in range(seed * 40))
+        off = [0] + cuts + [n]
+        docs = [raw[off[i]:off[i + 1]] for i in range(len(off) - 1)]
+        assert oracle.count(raw, off, utf8=True).as_dict() == re_count_utf8(docs)
+
+
+def test_utf8_multilingual_text():
+    """Words of several scripts; ASCII folding only (É stays, Z folds); punctuation of the
+    excluded blocks separates words; ASCII text gives the ASCII mode's table."""
+    text = ("Grüße aus Köln — naïve CAFÉ; Ωμέγα και άλφα… 日本語のテキスト、テスト。"
+            "Привет, мир! ‘quoted’ “double” 5×3÷2 Zebra zebra\ufeffword").encode("utf-8")
+    got = oracle.count(text, utf8=True).as_dict()
+    assert got == re_count_utf8([text])
+    assert got["grüße".encode()] == 1 and got["cafÉ".encode()] == 1
+    assert got[b"zebra"] == 2 and got["テスト".encode()] == 1
+    assert "日本語のテキスト".encode() in got and b"quoted" in got and b"word" in got
+    ascii_text = b"The quick brown fox, the lazy dog's tail; 42 THE"
+    assert oracle.count(ascii_text, utf8=True).as_dict() == oracle.count(ascii_text).as_dict()
