@@ -62,6 +62,192 @@ def cpu_baseline(corpus, sample_bytes: int):
                       f"({t.total} tokens, {len(t)} words) in {dt:.2f} s"}
 
 
+def cpu_parallel_baseline(corpus, sample_bytes: int):
+    """Time the paper's threaded CPU design (Section 3.1 map on threads, Section 3.2 merge;
+    oracle/cpu_parallel.cpp) on all host cores available to this process, on the same sample
+    as the oracle."""
+    import numpy as np
+    import oracle
+    host = corpus[:sample_bytes].cpu().numpy()
+    cores = len(os.sched_getaffinity(0))
+    oracle.lib()
+    _, total, secs = oracle.cpu_parallel(host, np.array([0, len(host)], dtype=np.int64), cores)
+    return {"value": round(len(host) / secs / 1e9, 4), "unit": "GB/s", "cores": cores,
+            "kind": "paper's CPU design (threads over byte ranges + parallel merge)",
+            "sample": f"first {len(host)} bytes of the {WORKLOAD} corpus ({total} tokens) "
+                      f"in {secs:.2f} s"}
+
+
+def device_copy_gbs(nbytes: int = 4 << 30, reps: int = 5) -> float:
+    """Measured device-to-device copy rate (read + write bytes / time), the practical HBM
+    ceiling beside the 8 TB/s specification."""
+    import torch
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def plain_1mb(steps: int):
+    """Workload "plain-1MB" (4 documents x 250,000 bytes, 5,000 words, Zipf 1.1, int32 counts):
+    microseconds per wc_count call with the text resident (host wall clock per call, which
+    includes the call's size readback), and the device time of the whole call (HIP events)."""
+    import torch
+    from paper_2206_05269_amd import synth, wc
+    c = synth.generate("plain-1MB")
+    t, o = c.text.to("cuda:0"), c.offsets.to("cuda:0")
+    plan = wc.count_plan(t.numel(), o.numel() - 1, count_bytes=4)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda:0")
+    for _ in range(5):
+        r = wc.count(t, o, count_bytes=4, workspace=ws)
+    if r.as_dict() != c.expected_table():
+        log("MISMATCH plain-1MB")
+        sys.exit(1)
+    n = max(50, steps * 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        wc.count(t, o, count_bytes=4, workspace=ws)
+    dt = (time.perf_counter() - t0) / n
+    dev = []
+    for _ in range(20):
+        r = wc.count(t, o, count_bytes=4, workspace=ws, debug_flags=wc.WC_DEBUG_TIME)
+        dev.append(r.res.total_ms)
+    dev_ms = sorted(dev)[len(dev) // 2]
+    B = t.numel()
+    res = {"workload": "plain-1MB", "bytes": B, "tokens": c.n_tokens, "words": r.n_entries,
+           "us_per_call": round(dt * 1e6, 1), "GBps": round(B / dt / 1e9, 2),
+           "device_us": round(dev_ms * 1e3, 1), "device_GBps": round(B / (dev_ms * 1e-3) / 1e9, 2)}
+    log(f"plain-1MB: {res['us_per_call']} us per call, device {res['device_us']} us")
+    return res
+
+
+def corpora_top50(steps: int):
+    """Workload "corpora-4x2000" (4 corpora x 2,000 documents, ~80 MB, 50,000 shared words,
+    200 words x5 per corpus): the four count tables and the top-50 distinctive words per corpus.
+    Times per call (host wall clock, text resident); checked against the generator."""
+    import torch
+    from paper_2206_05269_amd import synth, wc
+    cs = synth.generate("corpora-4x2000", device="cuda:0")
+    torch.cuda.synchronize()
+    B = sum(c.text.numel() for c in cs)
+    tabs = [wc.count(c.text, c.offsets, count_bytes=4) for c in cs]
+    for c, t in zip(cs, tabs):
+        if t.total_tokens != c.n_tokens or t.n_entries != int((c.expected > 0).sum()):
+            log("MISMATCH corpora-4x2000")
+            sys.exit(1)
+    wc.topk_ratio(tabs, 50)
+    n = max(5, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        tabs = [wc.count(c.text, c.offsets, count_bytes=4) for c in cs]
+    t_count = (time.perf_counter() - t0) / n
+    t0 = time.perf_counter()
+    for _ in range(n):
+        tk = wc.topk_ratio(tabs, 50)
+    t_topk = (time.perf_counter() - t0) / n
+    boosted = [set(int(x) for x in c.extra["boosted"]) for c in cs]
+    vocab = {bytes(cs[0].vocab[k, :cs[0].vocab_lens[k]]): k for k in range(len(cs[0].vocab_lens))}
+    planted = [sum(1 for w in tk.words[i] if vocab.get(w, -1) in boosted[i]) for i in range(len(cs))]
+    res = {"workload": "corpora-4x2000", "bytes": B, "tokens": sum(c.n_tokens for c in cs),
+           "count_ms": round(t_count * 1e3, 3), "count_GBps": round(B / t_count / 1e9, 2),
+           "topk_ms": round(t_topk * 1e3, 3), "k": 50, "vocab": int(tk.vocab_size),
+           "planted_in_top50": planted}
+    log(f"corpora-4x2000: counts {res['count_ms']} ms, top-50 {res['topk_ms']} ms, "
+        f"planted words in the top 50: {planted}")
+    return res
+
+
+def dense_vs_merge(steps: int):
+    """Section 3.3's reduce as the paper did it (a zero-padded words x documents matrix summed
+    by a row-sum kernel, wc_merge_dense) beside the hash merge (wc_merge), both on the
+    per-document table of one corpus of "corpora-4x2000" (2,000 documents, ~20 MB)."""
+    import torch
+    from paper_2206_05269_amd import synth, wc
+    c = synth.generate("corpora-4x2000", device="cuda:0")[0]
+    per = wc.count(c.text, c.offsets, per_doc=True, count_bytes=4)
+    a = wc.merge([per], count_bytes=8)
+    d = wc.merge_dense(per, count_bytes=8)
+    if a.n_entries != d.n_entries or a.total_tokens != c.n_tokens:
+        log("MISMATCH dense reduce")
+        sys.exit(1)
+    n = max(5, steps)
+    t_m, t_d, k_d, k_m = [], [], [], []
+    for _ in range(n):
+        t0 = time.perf_counter()
+        r = wc.merge([per], count_bytes=8, debug_flags=wc.WC_DEBUG_TIME)
+        t_m.append(time.perf_counter() - t0)
+        k_m.append(r.res.kernel_ms)
+        t0 = time.perf_counter()
+        r = wc.merge_dense(per, count_bytes=8, debug_flags=wc.WC_DEBUG_TIME)
+        t_d.append(time.perf_counter() - t0)
+        k_d.append(r.res.kernel_ms)
+    V, D = d.n_entries, int(per.res.n_docs)
+    res = {"workload": "corpora-4x2000 corpus 0", "docs": D, "doc_word_pairs": per.n_entries,
+           "words": V, "matrix_bytes": V * D * 4,
+           "merge_ms": round(sorted(t_m)[n // 2] * 1e3, 3),
+           "merge_insert_kernel_ms": round(sorted(k_m)[n // 2], 4),
+           "dense_ms": round(sorted(t_d)[n // 2] * 1e3, 3),
+           "rowsum_kernel_ms": round(sorted(k_d)[n // 2], 4),
+           "rowsum_GBps": round(V * D * 4 / (sorted(k_d)[n // 2] * 1e-3) / 1e9, 1),
+           "paper_v100_reduce_kernel_us": 4.29}
+    log(f"dense reduce: {res}")
+    return res
+
+
+def pinned_end_to_end(corpus, plan_kw, steps: int = 3, piece_bytes: int = 512 << 20):
+    """Config-3 text from pinned host memory, GB/s of text: the copy alone; one copy of the
+    whole 8 GiB, then the count; and wc_count_host, which copies 512 MiB pieces on a second
+    stream while the pieces before are counted."""
+    import torch
+    from paper_2206_05269_amd import wc
+    B = corpus.numel()
+    host = torch.empty(B, dtype=torch.uint8, pin_memory=True)
+    host.copy_(corpus)
+    dev = torch.empty_like(corpus)
+    off = torch.tensor([0, B], dtype=torch.int64, device="cuda:0")
+    dev.copy_(host, non_blocking=True)
+    wc.count(dev, off, **plan_kw)
+    torch.cuda.synchronize()
+    t_copy, t_all = [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        dev.copy_(host, non_blocking=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        wc.count(dev, off, **plan_kw)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_copy.append(t1 - t0)
+        t_all.append(t2 - t0)
+    t_pipe = []
+    kw = {k: v for k, v in plan_kw.items() if k in ("count_bytes", "table_slots")}
+    r = wc.count_host(host, piece_bytes=piece_bytes, d_text=dev, **kw)
+    n_words = r.n_entries
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = wc.count_host(host, piece_bytes=piece_bytes, d_text=dev, **kw)
+        torch.cuda.synchronize()
+        t_pipe.append(time.perf_counter() - t0)
+    del host, dev, r
+    tc, ta, tp = min(t_copy), min(t_all), min(t_pipe)
+    return {"h2d_GBps": round(B / tc / 1e9, 2),
+            "copy_then_count_GBps": round(B / ta / 1e9, 2), "copy_then_count_ms": round(ta * 1e3, 2),
+            "pipelined_GBps": round(B / tp / 1e9, 2), "pipelined_ms": round(tp * 1e3, 2),
+            "piece_bytes": piece_bytes, "words": n_words}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +259,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-fold", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the plain-1MB and corpora legs")
+    ap.add_argument("--no-pinned", action="store_true")
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--plain-docs", type=int, default=2000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -168,7 +356,23 @@ def main():
         sample = min(B, args.cpu_sample_mb << 20)
         log(f"timing the oracle on {sample} bytes")
         out["cpu_baseline"] = cpu_baseline(c.text, sample)
+        log(f"timing the paper's threaded CPU design on {sample} bytes")
+        out["cpu_parallel"] = cpu_parallel_baseline(c.text, sample)
+        log(f"parallel CPU: {out['cpu_parallel']['value']} GB/s on {out['cpu_parallel']['cores']} cores")
+    if not args.no_pinned:
+        kw2 = dict(count_bytes=w.count_bytes, table_slots=slots, workspace=ws, regrow=False)
+        out["pinned_input"] = pinned_end_to_end(c.text, kw2)
+        log(f"pinned input: {out['pinned_input']}")
     del c, ws, r
+    torch.cuda.empty_cache()
+    copy = device_copy_gbs()
+    out["device_copy_GBps"] = round(copy, 1)
+    out["roofline"]["frac_of_measured_copy"] = round(achieved / copy, 4)
+    log(f"device copy {copy:.1f} GB/s")
+    if not args.no_small:
+        out["plain_1mb"] = plain_1mb(args.steps)
+        out["corpora"] = corpora_top50(args.steps)
+        out["dense_reduce"] = dense_vs_merge(args.steps)
     torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_docs_per_s(args.steps, args.warmup, args.plain_docs)
@@ -302,7 +506,17 @@ def batched_docs_per_s(steps: int, warmup: int, plain_docs: int):
     torch.cuda.synchronize()
     n_docs = c.offsets.numel() - 1
     B = c.text.numel()
-    b = wc.Batch(max_docs=n_docs, max_bytes=B, count_bytes=4,
+    # the autotuner's choice, timed on a calibration slice of the first 5,000 documents
+    cal = 5000
+    off_h = c.offsets[:cal + 1].cpu()
+    cal_text = c.text[:int(off_h[-1])].contiguous()
+    t0 = time.perf_counter()
+    tu = wc.autotune(cal_text, c.offsets[:cal + 1].contiguous(), per_doc=True, count_bytes=4,
+                     use_cache=False)
+    t_tune = time.perf_counter() - t0
+    log(f"autotune: chunk {tu.chunk_bytes} lds {tu.lds_entries} load {tu.lds_load_pct}% "
+        f"in {t_tune:.1f} s")
+    b = wc.Batch(max_docs=n_docs, max_bytes=B, count_bytes=4, tuning=tu,
                  **wc.output_sizes(c.text, c.offsets, count_bytes=4))
     for _ in range(warmup):
         r = b.run(c.text, c.offsets)
@@ -337,7 +551,10 @@ def batched_docs_per_s(steps: int, warmup: int, plain_docs: int):
            "batched_docs_per_s": round(n_docs / dt_b, 1), "batched_ms": round(dt_b * 1e3, 3),
            "batched_GBps": round(B / dt_b / 1e9, 2),
            "plain_docs_per_s": round(1.0 / dt_p, 1), "plain_sample_docs": m,
-           "speedup": round((n_docs / dt_b) * dt_p, 1)}
+           "speedup": round((n_docs / dt_b) * dt_p, 1),
+           "tuning": {"chunk_bytes": tu.chunk_bytes, "lds_entries": tu.lds_entries,
+                      "relief_load_pct": tu.lds_load_pct, "calibration_docs": cal,
+                      "tune_s": round(t_tune, 1)}}
     log(f"batched {res['batched_docs_per_s']} docs/s vs plain {res['plain_docs_per_s']} docs/s")
     return res
 

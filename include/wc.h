@@ -71,6 +71,17 @@ typedef int32_t wc_status;
                                most 64 KiB (larger ones leave too few documents per CU, since
                                each document is counted by one workgroup), else as DIRECT */
 
+/* tokenisers (wc_opts.tokenizer) */
+#define WC_TOKENIZE_ASCII 0u  /* the tokeniser above: bytes >= 0x80 are delimiters */
+#define WC_TOKENIZE_UTF8  1u  /* the "other languages" of Section 5.2: a byte is a word byte
+                                 when it belongs to a well-formed UTF-8 sequence (Unicode,
+                                 Table 3-7) inside its document whose code point is a word
+                                 character: ASCII word bytes, or any code point from U+0080
+                                 except U+0080..U+00BF, U+00D7, U+00F7, U+2000..U+206F,
+                                 U+3000..U+303F and U+FEFF; folding stays ASCII-only. Counted
+                                 by the one-pass kernel (global, and per-document through one
+                                 (document, word) table); wc_batch_* take ASCII only */
+
 /* Launch tuning; a zero field takes the library default. */
 typedef struct wc_tuning {
   uint32_t stage_bytes;   /* bytes one workgroup scans per step: 4096 or 8192 (= 16 B/thread) */
@@ -91,6 +102,12 @@ typedef struct wc_opts {
   uint32_t debug_hash_bits;  /* 0 = full 64-bit keys; 1..63 keep only the low bits of every
                                 key, forcing key collisions so the byte compare decides */
   uint64_t word_bytes_cap;   /* capacity reserved for exported word bytes; 0 = auto */
+  uint64_t debug_count_bias; /* 0 normally; otherwise added to every exported count, so that
+                                the count-width check (WC_EOVERFLOW) and wide counts can be
+                                exercised without 2^31 tokens (the sums themselves are
+                                unchanged; total_tokens is not biased) */
+  uint32_t tokenizer;        /* WC_TOKENIZE_ASCII (0) or WC_TOKENIZE_UTF8 */
+  uint32_t reserved;         /* 0 */
 } wc_opts;
 
 typedef struct wc_plan {
@@ -121,6 +138,14 @@ typedef struct wc_result {
   uint64_t* d_docs;          /* WC_PER_DOC: uint64[n_entries], else NULL */
   float kernel_ms;           /* WC_DEBUG_TIME: duration of the count (or merge) kernel */
   float total_ms;            /* WC_DEBUG_TIME: duration of the whole call on the device */
+  /* Per-call statistics of the two-pass global count (zero for the other paths):
+   * [0] tokens written as records to the hash partitions (words missing the dictionary),
+   * [1] records pass 1 added straight to the global table because their partition's
+   *     arena region was used up,
+   * [2] dictionary words,
+   * [3] rounds a pass-1 wave waited for a partition ring slot or for a chunk to leave,
+   * [4] records pass 2 could not sum in its LDS table (added to the global table). */
+  uint64_t stats[5];
 } wc_result;
 
 /* Text of a status code (static storage). */
@@ -150,6 +175,27 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
                    uint64_t n_docs, const wc_opts* opts, void* d_workspace,
                    uint64_t workspace_bytes, wc_result* out, void* stream);
 
+/* Count a corpus that is in host memory, overlapping its transfer with the count (Section
+ * 4.1 names the host-to-device copy as the main cost of the GPU reduce): the text is cut into
+ * pieces of about piece_bytes (at least 1 MiB), each cut made right after an ASCII delimiter
+ * byte or at a document start so that no token spans two pieces; piece p+1 is copied on a
+ * second stream of the library while piece p is counted on `stream`, all into one global
+ * table exported once at the end. Same result as wc_count of the whole corpus.
+ *   h_corpus   host uint8[corpus_len] (pinned memory lets the copies run asynchronously);
+ *              read, never written; must stay valid until the call returns.
+ *   h_offsets  host uint64[n_docs + 1] document offsets.
+ *   d_text     device uint8[corpus_len] that receives the text ([offsets[0], offsets[n_docs])
+ *              is written); long words in the result refer to it, so it must outlive *out.
+ *   d_workspace of wc_count_host_plan() bytes.
+ * opts->mode must be WC_GLOBAL. Synchronous: returns when the table is exported. Errors as
+ * wc_count. */
+wc_status wc_count_host_plan(uint64_t corpus_len, uint64_t n_docs, const wc_opts* opts,
+                             uint64_t piece_bytes, wc_plan* out);
+wc_status wc_count_host(const uint8_t* h_corpus, uint64_t corpus_len, const uint64_t* h_offsets,
+                        uint64_t n_docs, const wc_opts* opts, uint64_t piece_bytes,
+                        uint8_t* d_text, void* d_workspace, uint64_t workspace_bytes,
+                        wc_result* out, void* stream);
+
 /* Plan a wc_merge of k tables (Section 3.3: the grouped counts of each word are summed).
  * Uses the inputs' host-side sizes only. */
 wc_status wc_merge_plan(const wc_result* const* tables, uint32_t k, const wc_opts* opts,
@@ -161,6 +207,21 @@ wc_status wc_merge_plan(const wc_result* const* tables, uint32_t k, const wc_opt
  * merging per-document tables equals counting the concatenation. Errors as wc_count. */
 wc_status wc_merge(const wc_result* const* tables, uint32_t k, const wc_opts* opts,
                    void* d_workspace, uint64_t workspace_bytes, wc_result* out, void* stream);
+
+/* The paper's reduce (Section 3.3; the "reduce on GPU" of the Section 4.1 table): the counts of
+ * a per-document table laid out as a zero-padded matrix with one row per distinct word and one
+ * column per document (uint32 cells, rows x n_docs x 4 bytes), and one kernel summing each
+ * row. Same result as wc_merge of that table (a global table, pointwise sums over the
+ * documents); kept as the comparison point the paper measured. per_doc must be a WC_PER_DOC
+ * table (its d_docs is read). wc_merge_dense_plan gives the workspace for a matrix of `rows`
+ * rows (0 = per_doc->n_entries, an upper bound of the distinct words). When the matrix of
+ * the actual distinct words does not fit the workspace, wc_merge_dense returns WC_ENOMEM with
+ * out->n_entries = the rows needed (plan again with them). WC_DEBUG_TIME: out->kernel_ms is
+ * the row-sum kernel alone, out->total_ms the whole call. Errors as wc_merge. */
+wc_status wc_merge_dense_plan(const wc_result* per_doc, const wc_opts* opts, uint64_t rows,
+                              uint64_t* workspace_bytes);
+wc_status wc_merge_dense(const wc_result* per_doc, const wc_opts* opts, void* d_workspace,
+                         uint64_t workspace_bytes, wc_result* out, void* stream);
 
 /* Per-corpus distinctive words (Section 4.3 compares presidents by the words each uses more
  * than the others). Over n corpora with joint vocabulary V (the union of their words): for
@@ -224,10 +285,14 @@ wc_status wc_batch_destroy(wc_batch* b);
 
 /* Serving. A server counts texts submitted at any time and keeps each result resident on
  * the device until released, answering merge queries over resident tables. It owns one
- * device pool of mem_budget bytes (allocated at creation); a request waits for admission
- * until the memory its count needs is free (requests larger than the budget fail with
- * WC_ENOMEM at submission; when the pool is held by resident tables and nothing is running,
- * the request fails with WC_ENOMEM instead of waiting). max_streams worker threads (1..16)
+ * device pool of mem_budget bytes (allocated at creation): count memory (text, offsets,
+ * workspace) is taken from its low end and resident tables from its high end. A request
+ * waits for admission until the memory its count needs is free, as long as some running
+ * request holds count memory (it will return it); requests larger than the budget fail with
+ * WC_ENOMEM at submission, and a request fails with WC_ENOMEM when nothing runs and resident
+ * tables leave no block large enough (only wc_server_release can free them). A finished count
+ * waits for its resident block while another running request can still return memory, and
+ * fails with WC_ENOMEM otherwise. max_streams worker threads (1..16)
  * each drive one HIP stream, so admitted requests overlap on the device; small
  * single-document requests queued together are counted in one per-document launch and split
  * into one table per request. Results are global word tables in the server's memory, valid
@@ -255,11 +320,15 @@ wc_status wc_server_wait(wc_server* s, uint64_t id, wc_result* out);
 wc_status wc_server_times(wc_server* s, uint64_t id, double* submit_s, double* start_s,
                           double* done_s);
 
-/* Queue the merge of k completed resident tables (Section 3.3) into a new resident table. */
+/* Queue the merge of k resident tables (Section 3.3) into a new resident table. The inputs
+ * must be requests of this server that have not been released (WC_EINVAL otherwise); they are
+ * pinned at submission, so releasing one before the merge has read it defers freeing its
+ * memory until the merge is done. */
 wc_status wc_server_merge(wc_server* s, const uint64_t* ids, uint32_t k, const wc_opts* opts,
                           uint64_t* new_id);
 
-/* Wait for request id, then free its resident table. */
+/* Wait for request id, then release it: its id is no longer valid and its resident table is
+ * freed (once no queued or running merge still reads it). */
 wc_status wc_server_release(wc_server* s, uint64_t id);
 
 /* Count launches the server has made (packing makes this smaller than the requests). */
@@ -269,7 +338,8 @@ wc_status wc_server_destroy(wc_server* s);
 
 /* Autotuner: time wc_count on a calibration sample (device-resident, as wc_count) for each
  * point of a small grid of launch tunings (per-document mode: work-item bytes x LDS entries x
- * relief load; global mode: LDS entries x load) with HIP events on `stream`, and return the
+ * relief load; global mode: LDS entries x flush load x flush policy) with HIP events on
+ * `stream`, and return the
  * fastest in *best (its time per call in *best_ms). The workspace must hold
  * wc_autotune_plan() bytes. The sample's counts are not returned. Output and private-table
  * sizes come from opts (word_bytes_cap, table_slots) as in wc_count; a grid point that runs
@@ -285,6 +355,16 @@ wc_status wc_autotune(const uint8_t* d_sample, uint64_t len, const uint64_t* d_o
  * each). Any output pointer may be NULL to skip it. */
 wc_status wc_table_to_host(const wc_result* t, uint64_t* word_offsets, uint8_t* words,
                            void* counts);
+
+/* Host helper: canonical order of a table copied to host memory (for example by
+ * wc_table_to_host): perm[i] = the entry that comes i-th when the entries are ordered by
+ * document (docs may be NULL for a global table), then by word bytes, unsigned and bytewise,
+ * a proper prefix first. word_offsets[n + 1] as stored (word e is words[word_offsets[e] -
+ * word_offsets[0] .. word_offsets[e+1] - word_offsets[0])), docs[n] or NULL, perm[n] out.
+ * The library's entry order is unspecified; this is the order to compare tables in. No
+ * device work. Errors: WC_EINVAL (null pointers, decreasing offsets). */
+wc_status wc_sort_canonical(uint64_t n, const uint64_t* word_offsets, const uint8_t* words,
+                            const uint64_t* docs, uint64_t* perm);
 
 /* FNV-1a 64 (Fowler, Noll, Vo) of n byte strings on the device: d_out[i] = FNV-1a 64 of
  * fold(d_bytes[d_offsets[i] .. d_offsets[i+1])), computed by the same device function the

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwc.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["wc_count.hip", "wc_global.hip", "wc_docs.hip", "wc_table.hip", "wc_api.hip", "wc_server.hip",
-           "wc_fold.hip"]
+           "wc_fold.hip", "wc_dense.hip"]
 ARCH = os.environ.get("WC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

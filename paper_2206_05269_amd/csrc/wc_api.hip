@@ -94,6 +94,7 @@ bool opts_ok(const wc_opts* o) {
   if (o->mode != WC_GLOBAL && o->mode != WC_PER_DOC) return false;
   if (o->table_slots && (!is_pow2(o->table_slots) || o->table_slots < 64)) return false;
   if (o->debug_hash_bits > 63) return false;
+  if (o->tokenizer != WC_TOKENIZE_ASCII && o->tokenizer != WC_TOKENIZE_UTF8) return false;
   return true;
 }
 
@@ -103,7 +104,6 @@ uint64_t key_mask_of(const wc_opts* o) {
 
 struct CountLayout {
   uint64_t S, n_stages, n_blocks, word_cap;
-  size_t sort_bytes = 0, scan_bytes = 0;
   Header* hdr;
   Slot* table;
   uint64_t* stage_doc;
@@ -113,7 +113,8 @@ struct CountLayout {
   uint8_t* words;
   // per-document
   uint64_t *docs, *doc_ptr, *doc_len, *list_docs, *list_slots, *sorted_docs, *sorted_slots, *lens;
-  void* cub;
+  uint64_t* doc_fill;  // per-document scatter cursors
+  uint64_t* sums;  // scan block totals
   // two-pass global count
   bool spill = false;
   uint32_t spill_grid = 0, R = 0, static_blocks = 0, dict_cap = 0;
@@ -130,6 +131,7 @@ struct CountLayout {
 
 bool use_spill(uint64_t len, const wc_opts* o) {
   if (o->mode != WC_GLOBAL) return false;
+  if (o->tokenizer == WC_TOKENIZE_UTF8) return false;  // the one-pass kernel reads UTF-8
   if (o->debug_flags & WC_DEBUG_SPILL) return true;
   if (o->debug_flags & (WC_DEBUG_DIRECT | WC_DEBUG_NO_LDS)) return false;
   return len >= kSpillMinBytes;
@@ -170,6 +172,7 @@ struct DocLayout {
 // text over every CU.
 bool use_doc_kernel(const wc_opts* o, uint64_t len, uint64_t n_docs) {
   if (o->mode != WC_PER_DOC || (o->debug_flags & WC_DEBUG_DIRECT)) return false;
+  if (o->tokenizer == WC_TOKENIZE_UTF8) return false;  // the one-pass kernel reads UTF-8
   if (o->debug_flags & WC_DEBUG_DOCS) return true;
   return n_docs == 0 || len / n_docs <= kDocKernelMaxMean;
 }
@@ -219,11 +222,22 @@ DocParams doc_params(const DocLayout& L, const wc_opts* o, uint32_t lds, uint32_
   P.arena = L.arena;
   P.arena_slots = L.arena_slots;
   P.key_mask = key_mask_of(o);
+  P.count_bias = o->debug_count_bias;
   return P;
 }
 
+// Caller-owned output arrays (the allocation-free entry point); NULL: they come from the
+// workspace.
+struct OutBufs {
+  uint64_t* woff;
+  void* counts;
+  uint8_t* words;
+  uint64_t word_cap;
+};
+
 bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& tu,
-                  const uint8_t* corpus, void* ws, CountLayout* L) {
+                  const uint8_t* corpus, void* ws, CountLayout* L,
+                  const OutBufs* outs = nullptr) {
   const bool per_doc = o->mode == WC_PER_DOC;
   uint64_t S = o->table_slots;
   if (!S) {
@@ -248,12 +262,18 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
   L->table = B.take<Slot>(S * sizeof(Slot));
   L->stage_doc = B.take<uint64_t>((L->n_stages + 2) * 8);
   L->bsum = B.take<uint64_t>(L->n_blocks * 16);
-  L->woff = B.take<uint64_t>((S + 1) * 8);
-  L->counts = B.take<uint8_t>(S * o->count_bytes);
-  L->words = B.take<uint8_t>(L->word_cap);
+  if (outs) {
+    L->woff = outs->woff;
+    L->counts = outs->counts;
+    L->words = outs->words;
+    L->word_cap = outs->word_cap;
+  } else {
+    L->woff = B.take<uint64_t>((S + 1) * 8);
+    L->counts = B.take<uint8_t>(S * o->count_bytes);
+    L->words = B.take<uint8_t>(L->word_cap);
+  }
   L->docs = L->doc_ptr = L->doc_len = L->list_docs = L->list_slots = L->sorted_docs =
-      L->sorted_slots = L->lens = nullptr;
-  L->cub = nullptr;
+      L->sorted_slots = L->lens = L->doc_fill = L->sums = nullptr;
   if (per_doc) {
     L->docs = B.take<uint64_t>(S * 8);
     L->doc_ptr = B.take<uint64_t>((n_docs + 1) * 8);
@@ -263,13 +283,8 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
     L->sorted_docs = B.take<uint64_t>(S * 8);
     L->sorted_slots = B.take<uint64_t>(S * 8);
     L->lens = B.take<uint64_t>((S + 1) * 8);
-    size_t a = 0, b = 0;
-    if (sort_pairs_u64(nullptr, &a, nullptr, nullptr, nullptr, nullptr, S, 64, 0) != hipSuccess)
-      return false;
-    if (excl_sum_u64(nullptr, &b, nullptr, nullptr, S + 1, 0) != hipSuccess) return false;
-    L->sort_bytes = a;
-    L->scan_bytes = b;
-    L->cub = B.take<uint8_t>(std::max(a, b));
+    L->doc_fill = B.take<uint64_t>((n_docs + 1) * 8);
+    L->sums = B.take<uint64_t>(std::max(excl_scan_scratch(S + 1), excl_scan_scratch(n_docs)));
   }
   L->spill = use_spill(len, o) && L->n_stages > 0;
   if (L->spill) {
@@ -342,6 +357,15 @@ hipError_t ensure_smem_attr() {
   }();
   return once;
 }
+
+// phases of count_table: all three for a plain call; a corpus counted in pieces clears once,
+// counts each piece into the same table and exports once
+constexpr unsigned kPhaseClear = 1u, kPhaseCount = 2u, kPhaseExport = 4u;
+constexpr unsigned kPhaseAll = kPhaseClear | kPhaseCount | kPhaseExport;
+
+wc_status count_table(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t* d_offsets,
+                      uint64_t n_docs, const wc_opts* opts, const Tune& tu, const CountLayout& L,
+                      wc_result* out, hipStream_t s, unsigned phases = kPhaseAll);
 
 wc_status finish_flags(const Header& h) {
   if (h.flags & kFlagBadOffsets) return WC_EINVAL;
@@ -458,15 +482,30 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
   CountLayout L;
   if (!layout_count(corpus_len, n_docs, opts, tu, d_corpus, d_workspace, &L)) return WC_EDEVICE;
   if (L.total > workspace_bytes) return WC_ENOMEM;
+  return count_table(d_corpus, corpus_len, d_offsets, n_docs, opts, tu, L, out, s);
+}
 
+}  // extern "C"
+
+namespace {
+
+// The table path of wc_count (one global table, or one (document, word) table sorted into a
+// CSR) over a laid-out workspace: clear, count (one- or two-pass), export. `phases` selects
+// the steps (a global count in pieces: clear with the first piece, export after the last).
+wc_status count_table(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t* d_offsets,
+                      uint64_t n_docs, const wc_opts* opts, const Tune& tu, const CountLayout& L,
+                      wc_result* out, hipStream_t s, unsigned phases) {
+  const bool per_doc = opts->mode == WC_PER_DOC;
   Timer tm;
-  HIPCHK(tm.init(opts->debug_flags & WC_DEBUG_TIME));
+  HIPCHK(tm.init((opts->debug_flags & WC_DEBUG_TIME) && phases == kPhaseAll));
   if (tm.on) HIPCHK(hipEventRecord(tm.c, s));
 
-  HIPCHK(launch_fill_zero(L.hdr, sizeof(Header), s));
-  HIPCHK(launch_fill_zero(L.table, L.S * sizeof(Slot), s));
+  if (phases & kPhaseClear) {
+    HIPCHK(launch_fill_zero(L.hdr, sizeof(Header), s));
+    HIPCHK(launch_fill_zero(L.table, L.S * sizeof(Slot), s));
+  }
   const uint64_t occ_limit = L.S - L.S / 8;
-  if (corpus_len && n_docs) {
+  if ((phases & kPhaseCount) && corpus_len && n_docs) {
     HIPCHK(launch_validate(d_offsets, n_docs, corpus_len, L.hdr, s));
     const int64_t b0 = base_offset(d_corpus);
     HIPCHK(launch_stage_doc(d_offsets, n_docs, b0, tu.stage, L.n_stages, L.stage_doc, s));
@@ -493,6 +532,8 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
     P.lds_flush_at = tu.flush_at;
     P.policy = tu.policy;
     P.no_lds = (opts->debug_flags & WC_DEBUG_NO_LDS) ? 1u : 0u;
+    P.utf8 = opts->tokenizer == WC_TOKENIZE_UTF8 ? 1u : 0u;
+    P.pad0 = 0;
     size_t dyn = (size_t)tu.lds * (per_doc ? 24 : 20);
     if (!L.spill) {
       if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
@@ -537,6 +578,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
       HIPCHK(launch_global(G, tm.on ? tm.a : nullptr, tm.on ? tm.b : nullptr, s));
     }
   }
+  if (!(phases & kPhaseExport)) return WC_OK;
 
   ExportParams E;
   memset(&E, 0, sizeof(E));
@@ -546,6 +588,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
   E.block_sums = L.bsum;
   E.n_blocks = L.n_blocks;
   E.count_bytes = opts->count_bytes;
+  E.count_bias = opts->debug_count_bias;
   E.per_doc = per_doc ? 1u : 0u;
   if (!per_doc) {
     E.word_offsets = L.woff;
@@ -574,21 +617,15 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
   out->d_word_offsets = L.woff;
   out->d_words = L.words;
   out->d_counts = L.counts;
+  if (L.spill) memcpy(out->stats, h.stat, sizeof(out->stats));
 
   if (per_doc) {
     const uint64_t n = h.n_entries;
-    // group entries by document: radix sort (document, slot) pairs
-    int end_bit = 1;
-    while (end_bit < 64 && (n_docs >> end_bit)) ++end_bit;
-    size_t tb = L.sort_bytes;
-    if (n) {
-      HIPCHK(sort_pairs_u64(L.cub, &tb, L.list_docs, L.sorted_docs, L.list_slots, L.sorted_slots,
-                            n, end_bit, s));
-    }
-    HIPCHK(launch_doc_csr(L.sorted_docs, n, L.hdr, n_docs, L.doc_ptr, L.doc_len, s));
+    // group entries by document (counting sort), then word offsets by a prefix sum of lengths
+    HIPCHK(group_by_doc(L.list_docs, L.list_slots, n, n_docs, L.doc_ptr, L.doc_len, L.doc_fill,
+                        L.sums, L.sorted_docs, L.sorted_slots, s));
     HIPCHK(launch_slot_lens(L.table, L.sorted_slots, n, L.lens, s));
-    size_t sb = L.scan_bytes;
-    HIPCHK(excl_sum_u64(L.cub, &sb, L.lens, L.woff, n + 1, s));
+    HIPCHK(excl_scan_u64(L.lens, L.woff, n + 1, L.sums, s));
     uint64_t wb = 0;
     HIPCHK(hipMemcpyAsync(&wb, L.woff + n, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -597,7 +634,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
       return WC_ENOMEM;
     }
     HIPCHK(launch_slot_write(L.table, L.sorted_slots, n, L.woff, L.words, L.counts,
-                             opts->count_bytes, L.docs, L.hdr, s));
+                             opts->count_bytes, opts->debug_count_bias, L.docs, L.hdr, s));
     HIPCHK(hipMemcpyAsync(&h, L.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     h.word_bytes = wb;
@@ -619,6 +656,10 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
   }
   return finish_flags(h);
 }
+
+}  // namespace
+
+extern "C" {
 
 // ------------------------------------------------------------------------------------------
 // merge
@@ -725,6 +766,7 @@ wc_status wc_merge(const wc_result* const* tables, uint32_t k, const wc_opts* op
   E.word_cap = L.word_cap;
   E.counts = L.counts;
   E.count_bytes = cb;
+  E.count_bias = opts ? opts->debug_count_bias : 0;
   HIPCHK(launch_export(E, s));
   Header h;
   HIPCHK(hipMemcpyAsync(&h, L.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
@@ -969,6 +1011,7 @@ extern "C" {
 wc_status wc_batch_plan(const wc_opts* opts, uint64_t max_docs, uint64_t max_bytes,
                         uint64_t* workspace_bytes) {
   if (!opts_ok(opts) || !workspace_bytes || opts->mode != WC_PER_DOC) return WC_EINVAL;
+  if (opts->tokenizer != WC_TOKENIZE_ASCII) return WC_EINVAL;  // the batch kernel reads ASCII
   if (max_bytes >= (1ull << 32)) return WC_EINVAL;
   Tune tu;
   if (!resolve_tuning(opts->tuning, &tu)) return WC_EINVAL;
@@ -1090,8 +1133,12 @@ std::vector<wc_tuning> tune_grid(const wc_opts* o) {
       for (uint32_t lds : {2048u, 4096u})
         for (uint32_t pct : {60u, 85u}) g.push_back(wc_tuning{0, lds, 0, 0, pct, chunk});
   } else {
+    // one-pass kernel: LDS entries x flush load x flush policy (the two-pass kernels, from
+    // 256 MiB, take lds_entries as the dictionary size and ignore the rest)
     for (uint32_t lds : {2048u, 4096u})
-      for (uint32_t pct : {60u, 75u, 90u}) g.push_back(wc_tuning{0, lds, 0, 0, pct, 0});
+      for (uint32_t pct : {60u, 75u, 90u})
+        for (uint32_t pol : {WC_FLUSH_ALL, WC_FLUSH_BYPASS})
+          g.push_back(wc_tuning{0, lds, pol, 0, pct, 0});
   }
   return g;
 }
@@ -1147,6 +1194,350 @@ wc_status wc_autotune(const uint8_t* d_sample, uint64_t len, const uint64_t* d_o
   if (!found) return WC_ENOMEM;
   if (best_ms) *best_ms = best_t / 2;
   return WC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// dense reduce: the paper's zero-padded keys x documents matrix and a row-sum kernel
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct DenseLayout {
+  uint64_t S, n_blocks, word_cap, fixed, rows_cap;
+  Header* hdr;
+  Slot* table;
+  uint64_t* bsum;
+  uint64_t* slot_of_input;
+  uint64_t* entry_of_slot;
+  uint64_t* woff;
+  void* counts;
+  uint8_t* words;
+  uint32_t* matrix;
+};
+
+bool dense_input_ok(const wc_result* t) {
+  return t && t->mode == WC_PER_DOC && (t->count_bytes == 4 || t->count_bytes == 8) &&
+         (!t->n_entries || (t->d_word_offsets && t->d_words && t->d_counts && t->d_docs));
+}
+
+// rows: matrix rows to lay out; ws_bytes (when ws is set): the matrix takes what is left
+void layout_dense(const wc_result* t, const wc_opts* o, uint64_t rows, void* ws,
+                  uint64_t ws_bytes, DenseLayout* L) {
+  const uint64_t n = t->n_entries;
+  uint64_t S = o && o->table_slots ? o->table_slots : next_pow2(std::max<uint64_t>(4096, 2 * n));
+  L->S = S;
+  L->n_blocks = (S + kExportSpan - 1) / kExportSpan;
+  L->word_cap = std::max<uint64_t>(o && o->word_bytes_cap ? o->word_bytes_cap : t->word_bytes, 16);
+  const uint32_t cb = o ? o->count_bytes : 8;
+  Bump B(ws);
+  L->hdr = B.take<Header>(sizeof(Header));
+  L->table = B.take<Slot>(S * sizeof(Slot));
+  L->bsum = B.take<uint64_t>(L->n_blocks * 16);
+  L->slot_of_input = B.take<uint64_t>(std::max<uint64_t>(n, 1) * 8);
+  L->entry_of_slot = B.take<uint64_t>(S * 8);
+  L->woff = B.take<uint64_t>((S + 1) * 8);
+  L->counts = B.take<uint8_t>(S * cb);
+  L->words = B.take<uint8_t>(L->word_cap);
+  L->fixed = B.off;
+  L->matrix = B.take<uint32_t>(0);
+  const uint64_t row_bytes = std::max<uint64_t>(t->n_docs, 1) * 4;
+  L->rows_cap = ws ? (ws_bytes > L->fixed ? (ws_bytes - L->fixed) / row_bytes : 0) : rows;
+  (void)rows;
+}
+
+}  // namespace
+
+extern "C" {
+
+wc_status wc_merge_dense_plan(const wc_result* per_doc, const wc_opts* opts, uint64_t rows,
+                              uint64_t* workspace_bytes) {
+  if (!workspace_bytes || !dense_input_ok(per_doc)) return WC_EINVAL;
+  if (opts && (opts->count_bytes != 4 && opts->count_bytes != 8)) return WC_EINVAL;
+  if (opts && opts->table_slots && !is_pow2(opts->table_slots)) return WC_EINVAL;
+  DenseLayout L;
+  if (!rows) rows = per_doc->n_entries;
+  layout_dense(per_doc, opts, rows, nullptr, 0, &L);
+  *workspace_bytes = L.fixed + rows * std::max<uint64_t>(per_doc->n_docs, 1) * 4;
+  return WC_OK;
+}
+
+wc_status wc_merge_dense(const wc_result* per_doc, const wc_opts* opts, void* d_workspace,
+                         uint64_t workspace_bytes, wc_result* out, void* stream) {
+  if (!out || !d_workspace || !dense_input_ok(per_doc)) return WC_EINVAL;
+  if (opts && (opts->count_bytes != 4 && opts->count_bytes != 8)) return WC_EINVAL;
+  if (opts && opts->table_slots && !is_pow2(opts->table_slots)) return WC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  DenseLayout L;
+  layout_dense(per_doc, opts, 0, d_workspace, workspace_bytes, &L);
+  if (L.fixed > workspace_bytes) return WC_ENOMEM;
+  const uint32_t cb = opts ? opts->count_bytes : 8;
+  const uint64_t n_docs = per_doc->n_docs;
+  Timer tm;
+  HIPCHK(tm.init(opts && (opts->debug_flags & WC_DEBUG_TIME)));
+  if (tm.on) HIPCHK(hipEventRecord(tm.c, s));
+  HIPCHK(launch_fill_zero(L.hdr, sizeof(Header), s));
+  HIPCHK(launch_fill_zero(L.table, L.S * sizeof(Slot), s));
+  MergeInput in;
+  in.word_offsets = per_doc->d_word_offsets;
+  in.words = per_doc->d_words;
+  in.counts = per_doc->d_counts;
+  in.n = per_doc->n_entries;
+  in.count_bytes = per_doc->count_bytes;
+  in.column = 0;
+  HIPCHK(launch_dense_keys(in, L.table, L.S - 1, L.S - L.S / 8, opts ? key_mask_of(opts) : ~0ull,
+                           L.hdr, L.slot_of_input, s));
+  ExportParams E;
+  memset(&E, 0, sizeof(E));
+  E.table = L.table;
+  E.slots = L.S;
+  E.hdr = L.hdr;
+  E.block_sums = L.bsum;
+  E.n_blocks = L.n_blocks;
+  E.word_offsets = L.woff;
+  E.words = L.words;
+  E.word_cap = L.word_cap;
+  E.counts = L.counts;
+  E.count_bytes = cb;
+  E.entry_of_slot = L.entry_of_slot;
+  HIPCHK(launch_export(E, s));
+  Header h;
+  HIPCHK(hipMemcpyAsync(&h, L.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  memset(out, 0, sizeof(*out));
+  if (h.flags) return finish_flags(h);
+  const uint64_t V = h.n_entries;
+  if (V > L.rows_cap) {
+    out->n_entries = V;  // rows the matrix needs: plan again with them
+    return WC_ENOMEM;
+  }
+  HIPCHK(launch_fill_zero(L.matrix, V * std::max<uint64_t>(n_docs, 1) * 4, s));
+  HIPCHK(launch_dense_scatter(in.n, L.slot_of_input, L.entry_of_slot, per_doc->d_docs,
+                              per_doc->d_counts, per_doc->count_bytes, n_docs, L.matrix, s));
+  if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
+  HIPCHK(launch_dense_rowsum(L.matrix, V, n_docs, L.counts, cb,
+                             opts ? opts->debug_count_bias : 0, L.hdr, s));
+  if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
+  HIPCHK(hipMemcpyAsync(&h, L.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out->n_entries = V;
+  out->total_tokens = per_doc->total_tokens;
+  out->word_bytes = h.word_bytes;
+  out->table_slots = L.S;
+  out->count_bytes = cb;
+  out->mode = WC_GLOBAL;
+  out->d_word_offsets = L.woff;
+  out->d_words = L.words;
+  out->d_counts = L.counts;
+  if (tm.on) {
+    HIPCHK(hipEventRecord(tm.d, s));
+    HIPCHK(hipEventSynchronize(tm.d));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, tm.a, tm.b));
+    out->kernel_ms = ms;
+    HIPCHK(hipEventElapsedTime(&ms, tm.c, tm.d));
+    out->total_ms = ms;
+  }
+  return finish_flags(h);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// canonical order of a host copy of a table (comparisons; no device work)
+// ------------------------------------------------------------------------------------------
+extern "C" wc_status wc_sort_canonical(uint64_t n, const uint64_t* word_offsets,
+                                       const uint8_t* words, const uint64_t* docs,
+                                       uint64_t* perm) {
+  if (n && (!word_offsets || !perm)) return WC_EINVAL;
+  if (!n) return WC_OK;
+  const uint64_t base = word_offsets[0];
+  for (uint64_t e = 0; e < n; ++e)
+    if (word_offsets[e + 1] < word_offsets[e]) return WC_EINVAL;
+  if (word_offsets[n] > base && !words) return WC_EINVAL;
+  std::vector<uint64_t> idx(n);
+  for (uint64_t e = 0; e < n; ++e) idx[e] = e;
+  std::sort(idx.begin(), idx.end(), [&](uint64_t a, uint64_t b) {
+    if (docs && docs[a] != docs[b]) return docs[a] < docs[b];
+    const uint64_t la = word_offsets[a + 1] - word_offsets[a];
+    const uint64_t lb = word_offsets[b + 1] - word_offsets[b];
+    const int c = memcmp(words + (word_offsets[a] - base), words + (word_offsets[b] - base),
+                         la < lb ? la : lb);
+    if (c) return c < 0;
+    if (la != lb) return la < lb;  // a proper prefix first
+    return a < b;
+  });
+  memcpy(perm, idx.data(), n * 8);
+  return WC_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// count from host memory: transfer pieces overlapped with the count of the pieces before
+// ------------------------------------------------------------------------------------------
+namespace {
+
+constexpr uint64_t kMinPiece = 1ull << 20;
+
+inline bool ascii_delimiter(uint8_t x) {
+  if (x >= 0x80) return false;  // may belong to a UTF-8 sequence: not taken as a cut
+  const uint8_t f = (x >= 'A' && x <= 'Z') ? (uint8_t)(x + 32) : x;
+  return !((f >= 'a' && f <= 'z') || (f >= '0' && f <= '9') || f == '\'');
+}
+
+// Cut [R0, R1) into pieces of about `piece` bytes, each cut right after an ASCII delimiter
+// byte (or at a document start), so that no token spans two pieces: every piece is then
+// counted on its own into the same table. Reads only the bytes just after each target.
+std::vector<uint64_t> plan_cuts(const uint8_t* h, const uint64_t* off, uint64_t n_docs,
+                                uint64_t piece) {
+  std::vector<uint64_t> cuts;
+  const uint64_t R0 = off[0], R1 = off[n_docs];
+  cuts.push_back(R0);
+  uint64_t d = 0;  // next document start to look at
+  while (cuts.back() < R1) {
+    uint64_t c = cuts.back() + piece;
+    if (c >= R1) {
+      cuts.push_back(R1);
+      break;
+    }
+    while (d <= n_docs && off[d] < c) ++d;
+    const uint64_t next_doc = d <= n_docs ? off[d] : R1;
+    while (c < next_doc && !ascii_delimiter(h[c - 1])) ++c;  // a token never spans a delimiter
+    cuts.push_back(std::min(c, next_doc));
+  }
+  return cuts;
+}
+
+struct HostPieces {
+  std::vector<uint64_t> cuts;     // piece p is [cuts[p], cuts[p+1])
+  std::vector<uint64_t> first;    // offsets of piece p start at first[p] in `offs`
+  std::vector<uint64_t> count;    // documents of piece p
+  std::vector<uint64_t> offs;     // per piece: offsets relative to the piece start
+  uint64_t max_len = 0, max_docs = 0;
+};
+
+void plan_pieces(const uint8_t* h, const uint64_t* off, uint64_t n_docs, uint64_t piece,
+                 HostPieces* P) {
+  P->cuts = plan_cuts(h, off, n_docs, piece);
+  uint64_t d = 1;  // first document start after the current cut
+  for (size_t p = 0; p + 1 < P->cuts.size(); ++p) {
+    const uint64_t a = P->cuts[p], b = P->cuts[p + 1];
+    P->first.push_back(P->offs.size());
+    P->offs.push_back(0);
+    while (d < n_docs && off[d] <= a) ++d;
+    for (; d < n_docs && off[d] < b; ++d) P->offs.push_back(off[d] - a);
+    P->offs.push_back(b - a);
+    P->count.push_back(P->offs.size() - P->first.back() - 1);
+    P->max_len = std::max(P->max_len, b - a);
+    P->max_docs = std::max(P->max_docs, P->count.back());
+  }
+}
+
+// Options of a count in pieces: the table is sized from the whole corpus (auto sizing would
+// size it from one piece), and so are the exported word bytes.
+wc_opts piece_opts(const wc_opts* o, uint64_t corpus_len) {
+  wc_opts q = *o;
+  q.debug_flags &= ~WC_DEBUG_TIME;
+  if (!q.table_slots) {
+    wc_plan p;
+    if (wc_count_plan(corpus_len, 1, o, &p) == WC_OK) q.table_slots = p.table_slots;
+  }
+  if (!q.word_bytes_cap) {
+    wc_plan p;
+    if (wc_count_plan(corpus_len, 1, &q, &p) == WC_OK) q.word_bytes_cap = p.word_bytes_cap;
+  }
+  return q;
+}
+
+}  // namespace
+
+extern "C" {
+
+wc_status wc_count_host_plan(uint64_t corpus_len, uint64_t n_docs, const wc_opts* opts,
+                             uint64_t piece_bytes, wc_plan* out) {
+  if (!opts_ok(opts) || !out || opts->mode != WC_GLOBAL) return WC_EINVAL;
+  const wc_opts q = piece_opts(opts, corpus_len);
+  // any piece is at most piece_bytes + the longest run without a delimiter; the layout of the
+  // whole corpus covers every piece's
+  wc_status st = wc_count_plan(corpus_len, n_docs, &q, out);
+  if (st != WC_OK) return st;
+  const uint64_t n_pieces = corpus_len / std::max<uint64_t>(piece_bytes, kMinPiece) + 2;
+  out->workspace_bytes += align_up((n_docs + 1 + 2 * n_pieces) * 8) + kAlign;
+  return WC_OK;
+}
+
+wc_status wc_count_host(const uint8_t* h_corpus, uint64_t corpus_len, const uint64_t* h_offsets,
+                        uint64_t n_docs, const wc_opts* opts, uint64_t piece_bytes,
+                        uint8_t* d_text, void* d_workspace, uint64_t workspace_bytes,
+                        wc_result* out, void* stream) {
+  if (!opts_ok(opts) || !out || !d_workspace || !h_offsets || opts->mode != WC_GLOBAL)
+    return WC_EINVAL;
+  if (corpus_len && (!h_corpus || !d_text)) return WC_EINVAL;
+  for (uint64_t d = 0; d < n_docs; ++d)
+    if (h_offsets[d] > h_offsets[d + 1]) return WC_EINVAL;
+  if (n_docs && h_offsets[n_docs] > corpus_len) return WC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(ensure_smem_attr());
+  const wc_opts q = piece_opts(opts, corpus_len);
+  Tune tu;
+  if (!resolve_tuning(q.tuning, &tu)) return WC_EINVAL;
+  HostPieces H;
+  if (n_docs) plan_pieces(h_corpus, h_offsets, n_docs, std::max<uint64_t>(piece_bytes, kMinPiece), &H);
+  // piece offset arrays at the end of the workspace, after the largest piece's layout
+  CountLayout L0;
+  global_stage(corpus_len, &q, &tu);
+  if (!layout_count(corpus_len, std::max<uint64_t>(n_docs, 1), &q, tu, nullptr, nullptr, &L0))
+    return WC_EDEVICE;
+  const uint64_t off_at = align_up(L0.total + kAlign);
+  if (off_at + H.offs.size() * 8 > workspace_bytes) return WC_ENOMEM;
+  uint64_t* d_offs = (uint64_t*)((uint8_t*)d_workspace + off_at);
+  if (!H.offs.empty())
+    HIPCHK(hipMemcpyAsync(d_offs, H.offs.data(), H.offs.size() * 8, hipMemcpyHostToDevice, s));
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  std::vector<hipEvent_t> ev(H.count.size(), nullptr);
+  wc_status st = WC_OK;
+  hipError_t e = hipSuccess;
+  CountLayout L;
+  // the table is cleared before the first piece (also for an empty corpus)
+  Tune t0 = tu;
+  global_stage(H.max_len, &q, &t0);
+  if (!layout_count(std::max<uint64_t>(H.max_len, 1), 1, &q, t0, d_text, d_workspace, &L))
+    st = WC_EDEVICE;
+  if (st == WC_OK) st = count_table(nullptr, 0, nullptr, 0, &q, t0, L, out, s, kPhaseClear);
+  for (size_t p = 0; st == WC_OK && e == hipSuccess && p < H.count.size(); ++p) {
+    const uint64_t a = H.cuts[p], n = H.cuts[p + 1] - a;
+    e = hipEventCreateWithFlags(&ev[p], hipEventDisableTiming);
+    if (e == hipSuccess && n) e = hipMemcpyAsync(d_text + a, h_corpus + a, n, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipEventRecord(ev[p], cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ev[p], 0);
+    if (e != hipSuccess) break;
+    Tune tp = tu;
+    global_stage(n, &q, &tp);
+    CountLayout Lp;
+    if (!layout_count(n, H.count[p], &q, tp, d_text + a, d_workspace, &Lp)) {
+      st = WC_EDEVICE;
+      break;
+    }
+    if (Lp.total > off_at || Lp.table != L.table || Lp.hdr != L.hdr) {
+      st = WC_ENOMEM;
+      break;
+    }
+    st = count_table(d_text + a, n, d_offs + H.first[p], H.count[p], &q, tp, Lp, out, s,
+                     kPhaseCount);
+  }
+  if (e == hipSuccess && st == WC_OK)
+    st = count_table(nullptr, 0, nullptr, 0, &q, t0, L, out, s, kPhaseExport);
+  hipError_t e2 = hipStreamSynchronize(cs);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  (void)hipStreamDestroy(cs);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) {
+    g_last_hip = (int32_t)e;
+    return WC_EDEVICE;
+  }
+  if (st == WC_OK) out->n_docs = n_docs;
+  return st;
 }
 
 }  // extern "C"

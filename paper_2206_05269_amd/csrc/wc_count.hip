@@ -34,15 +34,6 @@ struct LdsTable {
   uint32_t shift;   // 32 - log2(entries)
 };
 
-WC_DEV uint32_t lds_hash(uint64_t lo, uint64_t hi, uint32_t doc1) {
-  uint32_t a = (uint32_t)lo, b = (uint32_t)(lo >> 32), c = (uint32_t)hi, d = (uint32_t)(hi >> 32);
-  uint32_t h = a * 0x9E3779B1u ^ (b * 0x85EBCA77u) ^ (c * 0xC2B2AE3Du) ^ (d * 0x27D4EB2Fu) ^
-               (doc1 * 0x165667B1u);
-  h ^= h >> 15;
-  h *= 0x2C1B3C6Du;
-  h ^= h >> 13;
-  return h;
-}
 
 WC_DEV uint64_t lds_ld64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -63,7 +54,7 @@ WC_DEV bool lds_insert(const LdsTable& L, uint64_t lo, uint64_t hi, uint32_t doc
                        uint32_t* used) {
   constexpr int kMaxProbe = 32;
   const uint64_t hiw = hi | kTop;
-  uint32_t i = lds_hash(lo, hi, doc1) >> L.shift;
+  uint32_t i = lds_word_hash(lo, hi, doc1) >> L.shift;
   int probe = 0;
   bool active = true, ok = false;
   while (__any(active)) {
@@ -111,7 +102,102 @@ WC_DEV uint64_t short_key(uint64_t lo, uint64_t hi, uint32_t doc1, uint64_t key_
   return finish_key(h, key_mask);
 }
 
-template <int BLOCK, bool kPerDoc>
+// ---- UTF-8 tokeniser (the "other languages" of Section 5.2) ---------------------------------
+// A byte is a word byte when it belongs to a well-formed UTF-8 sequence (Unicode Standard,
+// Table 3-7) that lies inside one document and whose code point is a word character: the
+// ASCII word bytes, or any code point from U+0080 up except U+0080..U+00BF, U+00D7, U+00F7,
+// U+2000..U+206F, U+3000..U+303F and U+FEFF. Folding stays ASCII-only.
+WC_DEV bool utf8_word_cp(uint32_t cp) {
+  if (cp <= 0xBF || cp == 0xD7 || cp == 0xF7 || cp == 0xFEFF) return false;
+  if (cp >= 0x2000 && cp <= 0x206F) return false;
+  if (cp >= 0x3000 && cp <= 0x303F) return false;
+  return true;
+}
+
+// Sequence length (2..4) of a lead byte c, the allowed range of the byte after it and the
+// lead's code point bits; 0 when c does not start a multi-byte sequence.
+WC_DEV uint32_t utf8_lead(uint32_t c, uint32_t* lo2, uint32_t* hi2, uint32_t* v) {
+  *lo2 = 0x80u;
+  *hi2 = 0xBFu;
+  if (c >= 0xC2u && c <= 0xDFu) {
+    *v = c & 0x1Fu;
+    return 2;
+  }
+  if (c >= 0xE0u && c <= 0xEFu) {
+    *v = c & 0x0Fu;
+    if (c == 0xE0u) *lo2 = 0xA0u;
+    if (c == 0xEDu) *hi2 = 0x9Fu;
+    return 3;
+  }
+  if (c >= 0xF0u && c <= 0xF4u) {
+    *v = c & 0x07u;
+    if (c == 0xF0u) *lo2 = 0x90u;
+    if (c == 0xF4u) *hi2 = 0x8Fu;
+    return 4;
+  }
+  return 0;
+}
+
+// Word flag of the byte at logical position q under the UTF-8 reading. Bytes exist in
+// [lo, hi); byte_at(x) reads one, starts_at(x) tells whether a document starts at x (a
+// sequence never spans a document start).
+template <class ByteAt, class StartsAt>
+WC_DEV uint32_t utf8_word_byte(int64_t q, int64_t lo, int64_t hi, ByteAt byte_at,
+                               StartsAt starts_at) {
+  if (q < lo || q >= hi) return 0u;
+  uint32_t c = byte_at(q);
+  if (c < 0x80u) return is_word_byte(c) ? 1u : 0u;
+  int64_t j = q;
+  for (int k = 0; c >= 0x80u && c <= 0xBFu; ++k) {  // a continuation: step back to its lead
+    if (k == 3 || j == lo || starts_at(j)) return 0u;
+    c = byte_at(--j);
+  }
+  uint32_t lo2, hi2, v;
+  const uint32_t n = utf8_lead(c, &lo2, &hi2, &v);
+  if (n == 0 || j + (int64_t)n <= q) return 0u;
+  for (uint32_t t = 1; t < n; ++t) {
+    const int64_t x = j + t;
+    if (x >= hi || starts_at(x)) return 0u;
+    const uint32_t d = byte_at(x);
+    if (d < (t == 1 ? lo2 : 0x80u) || d > (t == 1 ? hi2 : 0xBFu)) return 0u;
+    v = (v << 6) | (d & 0x3Fu);
+  }
+  return utf8_word_cp(v) ? 1u : 0u;
+}
+
+// A document starts at logical position q (some offsets[d] == q, 1 <= d <= n_docs).
+WC_DEV bool doc_starts_at(const uint64_t* offsets, uint64_t n_docs, int64_t q) {
+  uint64_t a = 1, b = n_docs + 1;
+  while (a < b) {
+    const uint64_t m = (a + b) >> 1;
+    if ((int64_t)offsets[m] < q) a = m + 1;
+    else b = m;
+  }
+  return a <= n_docs && (int64_t)offsets[a] == q;
+}
+
+// A word starting at s that may run past the staged bytes, read from device memory under the
+// UTF-8 reading (up to `limit`, the document end): length, packed bytes (<= 16), FNV-1a 64.
+WC_DEV uint64_t scan_word_utf8(const uint8_t* corpus, uint64_t s, uint64_t limit, uint64_t* plo,
+                               uint64_t* phi, uint64_t* pfnv) {
+  auto byte_at = [&](int64_t x) -> uint32_t { return corpus[x]; };
+  auto starts_at = [&](int64_t) -> bool { return false; };  // none inside [s, limit)
+  uint64_t h = kFnvOffset, lo = 0, hi = 0, n = 0;
+  for (uint64_t p = s; p < limit; ++p) {
+    if (!utf8_word_byte((int64_t)p, (int64_t)s, (int64_t)limit, byte_at, starts_at)) break;
+    const uint32_t f = fold_byte(corpus[p]);
+    h = fnv_step(h, f);
+    if (n < 8) lo |= (uint64_t)f << (8 * n);
+    else if (n < 16) hi |= (uint64_t)f << (8 * (n - 8));
+    ++n;
+  }
+  *plo = lo;
+  *phi = hi;
+  *pfnv = h;
+  return n;
+}
+
+template <int BLOCK, bool kPerDoc, bool kUtf8>
 __global__ __launch_bounds__(BLOCK) void count_kernel(CountParams P) {
   constexpr int STAGE = BLOCK * 16;
   constexpr int NWAVE = BLOCK / 64;
@@ -190,8 +276,17 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(CountParams P) {
     return is_word_byte(P.corpus[q]) ? 1u : 0u;
   };
 
-  if (tid == 0) s_carry[(st0 & 1) ^ 1] = wflag_at(stage_pos(st0) - 1);
+  // UTF-8 reading of a byte outside the staged stage: device memory, document starts by search
+  auto g_byte = [&](int64_t x) -> uint32_t { return P.corpus[x]; };
+  auto g_start = [&](int64_t x) -> bool { return doc_starts_at(P.offsets, P.n_docs, x); };
+  if (tid == 0) {
+    const int64_t q = stage_pos(st0) - 1;
+    s_carry[(st0 & 1) ^ 1] = kUtf8 ? utf8_word_byte(q, R0, R1, g_byte, g_start) : wflag_at(q);
+  }
   for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
+  // the boundary bitmap is zero before any thread marks the first stage's document starts
+  // (a slow wave could otherwise clear a word after another wave marked a bit in it)
+  __syncthreads();
 
   uint4 cur = load16(st0);
   uint64_t tokens = 0;
@@ -209,7 +304,7 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(CountParams P) {
     uint32_t w16 = movemask4(f0) | (movemask4(f1) << 4) | (movemask4(f2) << 8) |
                    (movemask4(f3) << 12);
     const int64_t p = ls + tid * 16;
-    if (p < R0 || p + 16 > R1) {
+    if (!kUtf8 && (p < R0 || p + 16 > R1)) {
       int64_t lo_cut = R0 - p, hi_cut = R1 - p;
       uint32_t m = 0xffffu;
       if (lo_cut > 0) m &= lo_cut >= 16 ? 0u : (0xffffu << lo_cut) & 0xffffu;
@@ -217,8 +312,8 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(CountParams P) {
       w16 &= m;
     }
     s_txt4[tid] = make_uint4(g0, g1, g2, g3);
-    s_wm[tid] = (uint16_t)w16;
-    if (tid == 0) {
+    if (!kUtf8) s_wm[tid] = (uint16_t)w16;
+    if (!kUtf8 && tid == 0) {
       // flag of the first byte of the next stage
       int64_t q = le;
       uint32_t nw;
@@ -242,6 +337,23 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(CountParams P) {
     if (tid == 0 && c1 <= P.n_docs && (int64_t)P.offsets[c1] == le)
       atomicOr(&s_bnd[STAGE >> 5], 1u);
     __syncthreads();
+
+    if (kUtf8) {
+      // ---- 2b. UTF-8 word bytes: needs the staged bytes around each byte and the document
+      // starts of the stage (a sequence never spans one)
+      auto byte_at = [&](int64_t x) -> uint32_t {
+        return (x >= ls && x < le) ? (uint32_t)s_txt[x - ls] : (uint32_t)P.corpus[x];
+      };
+      auto starts_at = [&](int64_t x) -> bool {
+        if (x >= ls && x <= le) return (s_bnd[(x - ls) >> 5] >> ((x - ls) & 31)) & 1u;
+        return doc_starts_at(P.offsets, P.n_docs, x);
+      };
+      w16 = 0;
+      for (int j = 0; j < 16; ++j) w16 |= utf8_word_byte(p + j, R0, R1, byte_at, starts_at) << j;
+      s_wm[tid] = (uint16_t)w16;
+      if (tid == 0) s_next_w = utf8_word_byte(le, R0, R1, byte_at, starts_at);
+      __syncthreads();
+    }
 
     // ---- 3. start / last masks, compaction --------------------------------------------
     uint32_t prev = tid > 0 ? (s_wm[tid - 1] >> 15) : s_carry[(k & 1) ^ 1];
@@ -337,10 +449,19 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(CountParams P) {
         if (wl < 8) { lo &= (1ull << (8 * wl)) - 1; hi = 0; }
         else if (wl == 8) { hi = 0; }
         else if (wl < 16) { hi &= (1ull << (8 * (wl - 8))) - 1; }
-        bool done = use_lds && lds_insert<kPerDoc>(L, lo, hi, doc1, &s_used);
-        if (!done) {
-          uint64_t key = short_key<kPerDoc>(lo, hi, doc1, P.key_mask);
-          table_insert<kPerDoc>(P.table, P.mask, key, short_id(lo, hi, doc1), 1, hdr, P.occ_limit);
+        if (kUtf8 && !packable(lo, hi)) {
+          // a byte >= 0x80 where the packed form keeps its marks: stored as a long word
+          uint64_t h = fnv_packed(lo, hi, wl);
+          if (kPerDoc) h = fnv_u32(h, doc1 - 1);
+          table_insert<kPerDoc>(P.table, P.mask, finish_key(h, P.key_mask),
+                                long_id(P.corpus + (ls + s), wl, doc1), 1, hdr, P.occ_limit);
+        } else {
+          bool done = use_lds && lds_insert<kPerDoc>(L, lo, hi, doc1, &s_used);
+          if (!done) {
+            uint64_t key = short_key<kPerDoc>(lo, hi, doc1, P.key_mask);
+            table_insert<kPerDoc>(P.table, P.mask, key, short_id(lo, hi, doc1), 1, hdr,
+                                  P.occ_limit);
+          }
         }
       } else {
         // long word, or a word that continues past the stage: read it from device memory
@@ -353,8 +474,9 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(CountParams P) {
           limit = start + wl;
         }
         uint64_t lo, hi, h;
-        uint64_t n = scan_word(P.corpus, start, limit, &lo, &hi, &h);
-        if (n <= 16) {
+        uint64_t n = kUtf8 ? scan_word_utf8(P.corpus, start, limit, &lo, &hi, &h)
+                           : scan_word(P.corpus, start, limit, &lo, &hi, &h);
+        if (n <= 16 && (!kUtf8 || packable(lo, hi))) {
           bool done = use_lds && lds_insert<kPerDoc>(L, lo, hi, doc1, &s_used);
           if (!done) {
             uint64_t key = short_key<kPerDoc>(lo, hi, doc1, P.key_mask);
@@ -428,38 +550,39 @@ __global__ void read_range_kernel(const uint64_t* offsets, uint64_t n_docs, uint
   }
 }
 
-template <bool kPerDoc>
+template <bool kPerDoc, bool kUtf8>
 static hipError_t launch_count_t(const CountParams& P, uint32_t grid, uint32_t block,
                                  size_t dyn, hipStream_t s) {
   if (block == 512) {
-    hipLaunchKernelGGL((count_kernel<512, kPerDoc>), dim3(grid), dim3(512), dyn, s, P);
+    hipLaunchKernelGGL((count_kernel<512, kPerDoc, kUtf8>), dim3(grid), dim3(512), dyn, s, P);
   } else {
-    hipLaunchKernelGGL((count_kernel<256, kPerDoc>), dim3(grid), dim3(256), dyn, s, P);
+    hipLaunchKernelGGL((count_kernel<256, kPerDoc, kUtf8>), dim3(grid), dim3(256), dyn, s, P);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_count(const CountParams& P, bool per_doc, uint32_t grid, uint32_t block,
                         size_t dyn, hipStream_t s) {
-  return per_doc ? launch_count_t<true>(P, grid, block, dyn, s)
-                 : launch_count_t<false>(P, grid, block, dyn, s);
+  if (P.utf8)
+    return per_doc ? launch_count_t<true, true>(P, grid, block, dyn, s)
+                   : launch_count_t<false, true>(P, grid, block, dyn, s);
+  return per_doc ? launch_count_t<true, false>(P, grid, block, dyn, s)
+                 : launch_count_t<false, false>(P, grid, block, dyn, s);
 }
 
 hipError_t set_count_smem(uint32_t block, size_t dyn) {
+  const void* k512[4] = {(const void*)count_kernel<512, false, false>,
+                         (const void*)count_kernel<512, true, false>,
+                         (const void*)count_kernel<512, false, true>,
+                         (const void*)count_kernel<512, true, true>};
+  const void* k256[4] = {(const void*)count_kernel<256, false, false>,
+                         (const void*)count_kernel<256, true, false>,
+                         (const void*)count_kernel<256, false, true>,
+                         (const void*)count_kernel<256, true, true>};
   hipError_t e = hipSuccess;
-  if (block == 512) {
-    e = hipFuncSetAttribute((const void*)count_kernel<512, false>,
+  for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    e = hipFuncSetAttribute(block == 512 ? k512[i] : k256[i],
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)count_kernel<512, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-  } else {
-    e = hipFuncSetAttribute((const void*)count_kernel<256, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)count_kernel<256, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-  }
   return e;
 }
 

@@ -171,6 +171,27 @@ WC_DEV uint32_t packed_len(uint64_t lo, uint64_t hi) {
   return lo ? (uint32_t)((71 - __clzll(lo)) >> 3) : 0u;
 }
 
+// A word of <= 16 bytes can be stored packed (inline in a slot) when bytes 7 and 15 have
+// their top bit clear: the top bits of the two packed halves mark long words and published
+// slots. ASCII words always can; a UTF-8 word with a byte >= 0x80 there is stored as a long
+// word (a reference to its bytes) instead.
+WC_DEV bool packable(uint64_t lo, uint64_t hi) { return ((lo | hi) & kTop) == 0; }
+
+// 32-bit placement hash of a packed short word and its document (+1; 0 for a global table)
+// in per-workgroup LDS tables: multiply-xor of the four dwords and the document, then a
+// finishing mix (constants from xxHash's primes). Only decides where an entry is probed
+// first; counts never depend on it.
+WC_DEV uint32_t lds_word_hash(uint64_t lo, uint64_t hi, uint32_t doc1) {
+  const uint32_t a = (uint32_t)lo, b = (uint32_t)(lo >> 32), c = (uint32_t)hi,
+                 d = (uint32_t)(hi >> 32);
+  uint32_t h = a * 0x9E3779B1u ^ (b * 0x85EBCA77u) ^ (c * 0xC2B2AE3Du) ^ (d * 0x27D4EB2Fu) ^
+               (doc1 * 0x165667B1u);
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 13;
+  return h;
+}
+
 WC_DEV uint64_t finish_key(uint64_t h, uint64_t key_mask) {
   h &= key_mask;
   return h ? h : 1ull;

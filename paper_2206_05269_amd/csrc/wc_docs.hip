@@ -33,15 +33,6 @@ struct DocTable {
   uint32_t size;
 };
 
-WC_DEV uint32_t doc_hash(uint64_t lo, uint64_t hi, uint32_t doc1) {
-  uint32_t a = (uint32_t)lo, b = (uint32_t)(lo >> 32), c = (uint32_t)hi, d = (uint32_t)(hi >> 32);
-  uint32_t h = a * 0x9E3779B1u ^ (b * 0x85EBCA77u) ^ (c * 0xC2B2AE3Du) ^ (d * 0x27D4EB2Fu) ^
-               (doc1 * 0x165667B1u);
-  h ^= h >> 15;
-  h *= 0x2C1B3C6Du;
-  h ^= h >> 13;
-  return h;
-}
 
 // Count n occurrences of (doc1, word). Returns false when the table cannot take it (more
 // than `cap` live entries, or no slot within `max_probe` slots). Linear probing over groups of
@@ -52,7 +43,7 @@ WC_DEV bool doc_add(const DocTable& T, uint64_t lo, uint64_t hi, uint32_t doc1, 
                     uint32_t* live, uint32_t cap, uint32_t max_probe = 32) {
   const uint64_t hiw = hi | kTop;
   const uint32_t ng = T.size >> 2;  // groups of 4 slots (the size is a power of two >= 256)
-  uint32_t g = __umulhi(doc_hash(lo, hi, doc1), ng);
+  uint32_t g = __umulhi(lds_word_hash(lo, hi, doc1), ng);
   uint32_t probe = 0;
   bool active = true, ok = false;
   while (__any(active)) {
@@ -303,8 +294,15 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       uint32_t wl = packed_len(klo[j], khi[j]);
       if (room) {
         P.word_offsets[e] = bpos;
-        if (P.count_bytes == 4) ((int32_t*)P.counts)[e] = (int32_t)kc[j];
-        else ((int64_t*)P.counts)[e] = (int64_t)kc[j];
+        // a document has fewer than 2^31 tokens (the corpus is below 4 GiB), so only a
+        // debug bias can take an LDS count past the 32-bit width
+        const uint64_t c = (uint64_t)kc[j] + P.count_bias;
+        if (P.count_bytes == 4) {
+          if (c > 0x7fffffffull) or32(&hdr->flags, kFlagCountOverflow);
+          ((int32_t*)P.counts)[e] = (int32_t)c;
+        } else {
+          ((int64_t*)P.counts)[e] = (int64_t)c;
+        }
         P.docs[e] = d_first + kd[j] - 1;
         put_packed(P.words + bpos, klo[j], khi[j], wl);
       }
@@ -440,11 +438,12 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       if (sl.key && room) {
         uint64_t e = e_run + en, bp = b_run + eb;
         P.word_offsets[e] = bp;
+        const uint64_t c = sl.cnt + P.count_bias;
         if (P.count_bytes == 4) {
-          if (sl.cnt > 0x7fffffffull) or32(&hdr->flags, kFlagCountOverflow);
-          ((int32_t*)P.counts)[e] = (int32_t)sl.cnt;
+          if (c > 0x7fffffffull) or32(&hdr->flags, kFlagCountOverflow);
+          ((int32_t*)P.counts)[e] = (int32_t)c;
         } else {
-          ((int64_t*)P.counts)[e] = (int64_t)sl.cnt;
+          ((int64_t*)P.counts)[e] = (int64_t)c;
         }
         P.docs[e] = d;
         if (sl.w0 & kTop) {
@@ -484,6 +483,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
         const int64_t k1 = (B - base_off + STAGE - 1) / STAGE;
         if (tid == 0) s_carry[(k0 & 1) ^ 1] = 0;  // A is a document start
         for (int i = tid; i < STAGE / 32 + 2; i += BLOCK) s_bnd[i] = 0;
+        __syncthreads();  // cleared before any thread marks the first stage's document starts
         uint4 cur = load16(base_off + k0 * STAGE + tid * 16);
         for (int64_t k = k0; k < k1; ++k) {
           const int64_t ls = base_off + k * STAGE, le = ls + STAGE;

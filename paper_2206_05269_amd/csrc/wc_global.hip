@@ -6,9 +6,9 @@
 // byte rate of the scan. So:
 //
 //   dictionary: a sample of the text (kSampleStages stages of 8 KiB spread evenly over it) is
-//     counted, and the most frequent words (up to kDictMax) become a read-only dictionary of
-//     8-slot tagged buckets. A word is found with one read of its bucket's tags and indices and
-//     one key read, with no insertion, eviction or probe loop.
+//     counted, and the most frequent words (up to kDictMax) become a read-only perfect hash
+//     (hash and displace): a word is found with one displacement read, one slot read and one
+//     key compare, with no insertion, eviction or probe loop.
 //   pass 1 (global_map_kernel): scan the text, each wave on its own 1 KiB stripes; a dictionary
 //     word is counted in LDS; any other token becomes a 16-byte record (its packed bytes) in one
 //     of 256 partitions chosen by a hash of the word. Records wait in an LDS ring per partition
@@ -252,6 +252,9 @@ WC_DEV uint32_t wave_incl_scan(uint32_t x) {
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  // opaque to the optimiser: a caller that subtracts its own term must not have the sum
+  // rebuilt from the shifted partials (which keeps each shift a separate move)
+  __asm__ volatile("" : "+v"(x));
   return x;
 }
 
@@ -934,15 +937,27 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   uint64_t tokens = 0;  // wave-uniform
   bool def = false;     // a word of the previous stripe runs over its end (wave-uniform) ...
   uint32_t def_s = 0;   // ... from prefix byte def_s
+  // no document starts in the wave's whole run and it lies inside [R0, R1): every stripe is
+  // plain, and the per-stripe cursor reads are skipped
+  bool run_plain = false;
+  if (nsw > 0) {
+    const uint64_t sa = sw0 / NW, sb = min((sw0 + nsw - 1) / NW + 1, n_stages);
+    run_plain = P.stage_doc[sa] == P.stage_doc[sb] && stripe_pos(0) >= R0 &&
+                stripe_pos(nsw) <= R1;
+  }
 
   for (uint64_t i = 0; i < nsw; ++i) {
     const int64_t p0 = stripe_pos(i);
-    const uint64_t stage = (sw0 + i) / NW;
     // documents starting in [p0, p0 + kStripe): the first at or after the stage start is
     // stage_doc[stage]
-    const uint64_t c0 = P.stage_doc[stage];
-    const uint64_t c2 = P.stage_doc[min(stage + 1, n_stages)];
-    const bool plain = c2 == c0 && p0 >= R0 && p0 + (int64_t)kStripe <= R1;
+    uint64_t c0 = 0, c2 = 0;
+    bool plain = run_plain;
+    if (!run_plain) {
+      const uint64_t stage = (sw0 + i) / NW;
+      c0 = P.stage_doc[stage];
+      c2 = P.stage_doc[min(stage + 1, n_stages)];
+      plain = c2 == c0 && p0 >= R0 && p0 + (int64_t)kStripe <= R1;
+    }
 
     // ---- classify ---------------------------------------------------------------------------
     uint32_t w16;

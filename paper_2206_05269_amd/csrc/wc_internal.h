@@ -28,6 +28,8 @@ struct CountParams {
   uint32_t lds_flush_at;
   uint32_t policy;
   uint32_t no_lds;
+  uint32_t utf8;             // WC_TOKENIZE_UTF8: the UTF-8 reading of word bytes
+  uint32_t pad0;
 };
 
 // two-pass global count (wc_global.hip)
@@ -137,6 +139,7 @@ struct DocParams {
   Slot* arena;             // private tables of large documents
   uint64_t arena_slots;
   uint64_t key_mask;
+  uint64_t count_bias;     // added to every exported count (debug; 0 normally)
 };
 hipError_t set_doc_smem(size_t dyn);
 hipError_t launch_docs(const DocParams& P, uint32_t grid, size_t dyn, hipStream_t s);
@@ -165,6 +168,7 @@ struct ExportParams {
   uint64_t* docs;            // per-document: entry document
   uint64_t* slot_of_entry;   // optional: entry -> slot (joint tables)
   uint64_t* entry_of_slot;   // optional: slot -> entry
+  uint64_t count_bias;       // added to every exported count (debug; 0 normally)
 };
 constexpr uint32_t kExportBlock = 256;
 constexpr uint32_t kExportItems = 4;  // slots per thread
@@ -176,16 +180,17 @@ hipError_t launch_slot_lens(const Slot* table, const uint64_t* slots, uint64_t n
                             hipStream_t s);
 hipError_t launch_slot_write(const Slot* table, const uint64_t* slots, uint64_t n,
                              const uint64_t* word_offsets, uint8_t* words, void* counts,
-                             uint32_t count_bytes, uint64_t* docs, Header* hdr, hipStream_t s);
-hipError_t sort_pairs_u64(void* temp, size_t* temp_bytes, const uint64_t* keys_in,
-                          uint64_t* keys_out, const uint64_t* vals_in, uint64_t* vals_out,
-                          uint64_t n, int end_bit, hipStream_t s);
-hipError_t excl_sum_u64(void* temp, size_t* temp_bytes, const uint64_t* in, uint64_t* out,
-                        uint64_t n, hipStream_t s);
-
-// per-document CSR: sort entries by document
-hipError_t launch_doc_csr(const uint64_t* docs_in, uint64_t n_entries_max, const Header* hdr,
-                          uint64_t n_docs, uint64_t* doc_ptr, uint64_t* doc_len, hipStream_t s);
+                             uint32_t count_bytes, uint64_t count_bias, uint64_t* docs,
+                             Header* hdr, hipStream_t s);
+// exclusive prefix sum of n uint64 values (out may be in); sums: excl_scan_scratch(n) bytes
+uint64_t excl_scan_scratch(uint64_t n);
+hipError_t excl_scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* sums,
+                         hipStream_t s);
+// entries (docs[e], slots[e]) grouped by document into sorted_*; doc_ptr / doc_len per
+// document; fill: n_docs scratch; sums: excl_scan_scratch(n_docs)
+hipError_t group_by_doc(const uint64_t* docs, const uint64_t* slots, uint64_t n, uint64_t n_docs,
+                        uint64_t* doc_ptr, uint64_t* doc_len, uint64_t* fill, uint64_t* sums,
+                        uint64_t* sorted_docs, uint64_t* sorted_slots, hipStream_t s);
 
 // ---- fills ---------------------------------------------------------------------------------
 hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t s);
@@ -202,6 +207,18 @@ struct MergeInput {
 hipError_t launch_merge_insert(const MergeInput& in, Slot* table, uint64_t mask,
                                uint64_t occ_limit, uint64_t key_mask, Header* hdr,
                                uint64_t* joint_counts, uint32_t n_columns, hipStream_t s);
+
+// ---- dense reduce (the zero-padded keys x documents matrix) --------------------------------
+hipError_t launch_dense_keys(const MergeInput& in, Slot* table, uint64_t mask,
+                             uint64_t occ_limit, uint64_t key_mask, Header* hdr,
+                             uint64_t* slot_of_input, hipStream_t s);
+hipError_t launch_dense_scatter(uint64_t n, const uint64_t* slot_of_input,
+                                const uint64_t* entry_of_slot, const uint64_t* docs,
+                                const void* counts, uint32_t count_bytes, uint64_t n_docs,
+                                uint32_t* matrix, hipStream_t s);
+hipError_t launch_dense_rowsum(const uint32_t* matrix, uint64_t rows, uint64_t n_docs,
+                               void* counts, uint32_t count_bytes, uint64_t bias, Header* hdr,
+                               hipStream_t s);
 
 // ---- top-k ---------------------------------------------------------------------------------
 struct TopkParams {

@@ -2,10 +2,11 @@
 // resident on the device and answers merge queries (Section 3.3's summation of grouped counts,
 // across requests).
 //
-// Admission. The server owns one device pool of `mem_budget` bytes and sub-allocates from it
-// (first fit). A request is admitted when the memory its count needs (text, offsets,
-// workspace) is free; until then it waits in arrival order. Results are compacted into an
-// exact-size resident block, and the rest of the request's memory is returned at once.
+// Admission. The server owns one device pool of `mem_budget` bytes; the policy (count memory
+// from the low end, resident tables from the high end, when to wait and when to fail) is the
+// host-only wc::Admission of wc_admission.h. A request is admitted when the memory its count
+// needs (text, offsets, workspace) is free; until then it waits in arrival order. Results are
+// compacted into an exact-size resident block, and the count memory is returned at once.
 //
 // Continuous batching. `max_streams` worker threads each own a HIP stream (default priority),
 // so admitted requests run concurrently on the device. A worker that takes a small
@@ -32,6 +33,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "wc_admission.h"
 #include "wc_internal.h"
 
 namespace {
@@ -41,55 +43,7 @@ using Clock = std::chrono::steady_clock;
 constexpr uint32_t kPackDocs = 64;
 constexpr uint64_t kPackBytes = 4ull << 20;
 constexpr uint64_t kSmallBytes = 1ull << 20;
-constexpr uint64_t kPoolAlign = 256;
 constexpr uint64_t kStageBytes = 8ull << 20;  // per pinned upload buffer (two per worker)
-
-// First-fit allocator over [0, size) of the device pool.
-class Pool {
- public:
-  void init(uint8_t* base, uint64_t size) {
-    base_ = base;
-    free_[0] = size;
-  }
-  uint8_t* alloc(uint64_t bytes) {
-    bytes = (bytes + kPoolAlign - 1) & ~(kPoolAlign - 1);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        uint64_t off = it->first, len = it->second;
-        free_.erase(it);
-        if (len > bytes) free_[off + bytes] = len - bytes;
-        used_[off] = bytes;
-        return base_ + off;
-      }
-    }
-    return nullptr;
-  }
-  void release(uint8_t* p) {
-    if (!p) return;
-    uint64_t off = (uint64_t)(p - base_);
-    auto u = used_.find(off);
-    if (u == used_.end()) return;
-    uint64_t len = u->second;
-    used_.erase(u);
-    auto nx = free_.lower_bound(off);
-    if (nx != free_.end() && nx->first == off + len) {
-      len += nx->second;
-      nx = free_.erase(nx);
-    }
-    if (nx != free_.begin()) {
-      auto pv = std::prev(nx);
-      if (pv->first + pv->second == off) {
-        pv->second += len;
-        return;
-      }
-    }
-    free_[off] = len;
-  }
-
- private:
-  uint8_t* base_ = nullptr;
-  std::map<uint64_t, uint64_t> free_, used_;
-};
 
 struct Request {
   uint64_t id = 0;
@@ -102,9 +56,11 @@ struct Request {
   bool merge = false;
   std::vector<uint64_t> merge_ids;
   // state
+  std::vector<std::shared_ptr<Request>> merge_inputs;  // pinned at submission
   int state = 0;  // 0 queued, 1 running, 2 done
   wc_status status = WC_EAGAIN;
   uint8_t* resident = nullptr;
+  wc::ResidentLife life;  // merges reading the resident table; released by the client
   wc_result res{};
   double t_submit = 0, t_start = 0, t_done = 0;
 };
@@ -119,7 +75,7 @@ struct wc_server {
   int device = 0;
   uint64_t budget = 0;
   uint8_t* pool_mem = nullptr;
-  Pool pool;
+  wc::Admission adm;
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_mem;
   std::deque<std::shared_ptr<Request>> queue;
@@ -136,8 +92,6 @@ struct wc_server {
   };
   std::vector<Staging> staging;  // one per worker
   uint64_t next_id = 1;
-  uint32_t holders = 0;  // requests holding count memory
-  uint32_t resident_waiters = 0;  // holders waiting in keep_resident for resident memory
   bool stop = false;
   std::atomic<uint64_t> launches{0};
 };
@@ -184,21 +138,21 @@ wc_status keep_resident(wc_server* S, wc_server::Staging& W, hipStream_t s, cons
     return WC_EDEVICE;
   const uint64_t b0 = W.small[0], nb = W.small[1] - W.small[0];
   const uint64_t bytes = (n + 1) * 8 + n * cb + nb + 64;
-  uint8_t* mem;
+  uint8_t* mem = nullptr;
   {
-    // This worker holds count memory. It waits only while another holder that is not itself
-    // waiting here can still return memory; otherwise (resident tables fill the budget) the
-    // request fails with WC_ENOMEM, so two workers never wait on each other.
+    // This worker holds count memory; the policy (wc::Admission::try_resident) lets it wait
+    // only while another holder that is not itself waiting here can still return memory.
     std::unique_lock<std::mutex> lk(S->mu);
-    mem = S->pool.alloc(bytes);
-    while (!mem && !S->stop && S->holders > S->resident_waiters + 1) {
-      ++S->resident_waiters;
+    uint64_t off = 0;
+    wc::Admit a;
+    while ((a = S->adm.try_resident(bytes, &off)) == wc::Admit::kWait && !S->stop) {
+      ++S->adm.resident_waiters;
       S->cv_mem.wait(lk);
-      --S->resident_waiters;
-      mem = S->pool.alloc(bytes);
+      --S->adm.resident_waiters;
     }
+    if (a != wc::Admit::kGranted) return WC_ENOMEM;
+    mem = S->pool_mem + off;
   }
-  if (!mem) return WC_ENOMEM;
   uint64_t* d_off = (uint64_t*)mem;
   uint8_t* d_cnt = mem + (((n + 1) * 8 + 15) & ~15ull);
   uint8_t* d_words = d_cnt + ((n * cb + 15) & ~15ull);
@@ -213,7 +167,8 @@ wc_status keep_resident(wc_server* S, wc_server::Staging& W, hipStream_t s, cons
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     std::lock_guard<std::mutex> lk(S->mu);
-    S->pool.release(mem);
+    S->adm.free_resident((uint64_t)(mem - S->pool_mem));
+    S->cv_mem.notify_all();
     return WC_EDEVICE;
   }
   R->resident = mem;
@@ -229,25 +184,36 @@ wc_status keep_resident(wc_server* S, wc_server::Staging& W, hipStream_t s, cons
   return WC_OK;
 }
 
-// Take count memory for a request, waiting while other requests hold count memory (they
-// will return it); when none does, the memory is held by resident tables, which only the
-// caller can release, so the request fails with WC_ENOMEM instead of waiting.
+// Take count memory for a request (wc::Admission::try_count): wait while other requests
+// hold count memory (they will return it); when none does, the memory is held by resident
+// tables, which only the client can release, so the request fails with WC_ENOMEM.
 uint8_t* pool_alloc_wait(wc_server* S, uint64_t bytes) {
   std::unique_lock<std::mutex> lk(S->mu);
-  uint8_t* p;
-  while (!(p = S->pool.alloc(bytes))) {
-    if (S->stop || S->holders == 0) return nullptr;
-    S->cv_mem.wait(lk);
-  }
-  ++S->holders;
-  return p;
+  uint64_t off = 0;
+  wc::Admit a;
+  while ((a = S->adm.try_count(bytes, &off)) == wc::Admit::kWait && !S->stop) S->cv_mem.wait(lk);
+  return a == wc::Admit::kGranted ? S->pool_mem + off : nullptr;
 }
 
 void pool_free(wc_server* S, uint8_t* p) {
   std::lock_guard<std::mutex> lk(S->mu);
-  S->pool.release(p);
-  --S->holders;
+  S->adm.free_count((uint64_t)(p - S->pool_mem));
   S->cv_mem.notify_all();
+}
+
+// Free a resident table (under the lock).
+void free_resident_locked(wc_server* S, Request* R) {
+  if (R->resident) S->adm.free_resident((uint64_t)(R->resident - S->pool_mem));
+  R->resident = nullptr;
+  S->cv_mem.notify_all();
+}
+
+// A merge is done with its inputs: a released input whose last reader this was is freed.
+void unpin_inputs(wc_server* S, Request* M) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (auto& in : M->merge_inputs)
+    if (in->life.unpin()) free_resident_locked(S, in.get());
+  M->merge_inputs.clear();
 }
 
 void finish(wc_server* S, Request* R, wc_status st) {
@@ -287,40 +253,36 @@ void run_group(wc_server* S, int idx, std::vector<std::shared_ptr<Request>>& G) 
   for (auto& r : G) r->t_start = t0;
   if (G.size() == 1 && G[0]->merge) {
     Request* R = G[0].get();
-    // inputs were submitted before the merge, so they are running or done: wait for them
+    // The inputs were pinned when the merge was submitted (a release defers freeing their
+    // resident tables until this merge is done); they were submitted before it, so they are
+    // running or done: wait for them.
     std::vector<const wc_result*> ins;
-    std::vector<std::shared_ptr<Request>> keep;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      for (uint64_t id : R->merge_ids) {
-        auto it = S->reqs.find(id);
-        if (it == S->reqs.end()) {
-          ins.clear();
-          break;
-        }
-        auto in = it->second;
+      for (auto& in : R->merge_inputs) {
         S->cv_done.wait(lk, [&] { return in->state == 2; });
         if (in->status != WC_OK) {
           ins.clear();
           break;
         }
-        keep.push_back(in);
         ins.push_back(&in->res);
       }
     }
-    if (ins.empty()) return finish(S, R, WC_EINVAL);
+    wc_status st = ins.empty() ? WC_EINVAL : WC_OK;
     wc_opts o = R->opts;
     wc_plan p;
-    wc_status st = wc_merge_plan(ins.data(), (uint32_t)ins.size(), &o, &p);
-    if (st != WC_OK) return finish(S, R, st);
-    uint8_t* ws = pool_alloc_wait(S, p.workspace_bytes);
-    if (!ws) return finish(S, R, WC_ENOMEM);
-    wc_result t;
-    st = wc_merge(ins.data(), (uint32_t)ins.size(), &o, ws, p.workspace_bytes, &t, s);
-    S->launches++;
-    if (st == WC_OK) st = keep_resident(S, S->staging[idx], s, t, 0, t.n_entries, R);
-    if (st == WC_OK) R->res.total_tokens = t.total_tokens;
-    pool_free(S, ws);
+    if (st == WC_OK) st = wc_merge_plan(ins.data(), (uint32_t)ins.size(), &o, &p);
+    uint8_t* ws = nullptr;
+    if (st == WC_OK && !(ws = pool_alloc_wait(S, p.workspace_bytes))) st = WC_ENOMEM;
+    if (st == WC_OK) {
+      wc_result t;
+      st = wc_merge(ins.data(), (uint32_t)ins.size(), &o, ws, p.workspace_bytes, &t, s);
+      S->launches++;
+      if (st == WC_OK) st = keep_resident(S, S->staging[idx], s, t, 0, t.n_entries, R);
+      if (st == WC_OK) R->res.total_tokens = t.total_tokens;
+    }
+    if (ws) pool_free(S, ws);
+    unpin_inputs(S, R);  // the merge's stream is synchronised: nothing reads the inputs now
     return finish(S, R, st);
   }
   // stage the texts on the device (one buffer for the group)
@@ -510,7 +472,7 @@ wc_status wc_server_create(int device, uint64_t mem_budget, uint32_t max_streams
     delete S;
     return WC_ENOMEM;
   }
-  S->pool.init(S->pool_mem, mem_budget);
+  S->adm.init(mem_budget);
   for (uint32_t i = 0; i < max_streams; ++i) {
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
@@ -612,6 +574,7 @@ wc_status wc_server_times(wc_server* S, uint64_t id, double* submit_s, double* s
 wc_status wc_server_merge(wc_server* S, const uint64_t* ids, uint32_t k, const wc_opts* opts,
                           uint64_t* new_id) {
   if (!S || !new_id || !ids || k == 0) return WC_EINVAL;
+  if (opts && opts->count_bytes != 4 && opts->count_bytes != 8) return WC_EINVAL;
   auto R = std::make_shared<Request>();
   R->merge = true;
   R->merge_ids.assign(ids, ids + k);
@@ -621,6 +584,13 @@ wc_status wc_server_merge(wc_server* S, const uint64_t* ids, uint32_t k, const w
   R->t_submit = now_s();
   {
     std::lock_guard<std::mutex> lk(S->mu);
+    // pin the inputs now: releasing one before the merge has read it defers the free
+    for (uint32_t i = 0; i < k; ++i) {
+      auto it = S->reqs.find(ids[i]);
+      if (it == S->reqs.end()) return WC_EINVAL;  // nothing pinned yet
+      R->merge_inputs.push_back(it->second);
+    }
+    for (auto& in : R->merge_inputs) in->life.pin();
     R->id = S->next_id++;
     S->reqs[R->id] = R;
     S->queue.push_back(R);
@@ -639,10 +609,11 @@ wc_status wc_server_release(wc_server* S, uint64_t id) {
     if (it == S->reqs.end()) return WC_EINVAL;
     R = it->second;
     S->cv_done.wait(lk, [&] { return R->state == 2; });
-    S->reqs.erase(it);
-    if (R->resident) S->pool.release(R->resident);
-    R->resident = nullptr;
-    S->cv_mem.notify_all();
+    auto again = S->reqs.find(id);  // the wait may have let another thread in
+    if (again == S->reqs.end() || again->second != R) return WC_EINVAL;
+    S->reqs.erase(again);
+    // a merge that will read the table frees it when done (ResidentLife)
+    if (R->life.release()) free_resident_locked(S, R.get());
   }
   return WC_OK;
 }

@@ -1,7 +1,6 @@
 // Table kernels: compaction of a hash table into dense arrays, per-document CSR grouping,
 // merging word tables (Section 3.3: grouped counts of one word are summed), the per-corpus
 // distinctive-word ranking (Section 4.3) and the FNV-1a 64 check entry point.
-#include <hipcub/hipcub.hpp>
 
 #include "wc_internal.h"
 
@@ -142,7 +141,7 @@ __global__ __launch_bounds__(kExportBlock) void export_write_kernel(ExportParams
     if (!sl[j].key) continue;
     const uint64_t i = first + j;
     uint64_t len = slot_len(sl[j]);
-    uint64_t c = E.per_doc ? (sl[j].cnt & 0xffffffffull) : sl[j].cnt;
+    uint64_t c = (E.per_doc ? (sl[j].cnt & 0xffffffffull) : sl[j].cnt) + E.count_bias;
     E.word_offsets[e] = pos;
     if (E.count_bytes == 4) {
       if (c > 0x7fffffffull) or32(&E.hdr->flags, kFlagCountOverflow);
@@ -213,11 +212,12 @@ __global__ void slot_lens_kernel(const Slot* table, const uint64_t* slots, uint6
 // Write entry e from slot slots[e]: count, document, word bytes at word_offsets[e].
 __global__ void slot_write_kernel(const Slot* table, const uint64_t* slots, uint64_t n,
                                   const uint64_t* word_offsets, uint8_t* words, void* counts,
-                                  uint32_t count_bytes, uint64_t* docs, Header* hdr) {
+                                  uint32_t count_bytes, uint64_t count_bias, uint64_t* docs,
+                                  Header* hdr) {
   uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (e >= n) return;
   Slot sl = table[slots[e]];
-  uint64_t c = sl.cnt & 0xffffffffull;
+  uint64_t c = (sl.cnt & 0xffffffffull) + count_bias;
   if (count_bytes == 4) {
     if (c > 0x7fffffffull) or32(&hdr->flags, kFlagCountOverflow);
     ((int32_t*)counts)[e] = (int32_t)c;
@@ -245,10 +245,12 @@ hipError_t launch_slot_lens(const Slot* table, const uint64_t* slots, uint64_t n
 
 hipError_t launch_slot_write(const Slot* table, const uint64_t* slots, uint64_t n,
                              const uint64_t* word_offsets, uint8_t* words, void* counts,
-                             uint32_t count_bytes, uint64_t* docs, Header* hdr, hipStream_t s) {
+                             uint32_t count_bytes, uint64_t count_bias, uint64_t* docs,
+                             Header* hdr, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(slot_write_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s,
-                     table, slots, n, word_offsets, words, counts, count_bytes, docs, hdr);
+                     table, slots, n, word_offsets, words, counts, count_bytes, count_bias, docs,
+                     hdr);
   return hipGetLastError();
 }
 
@@ -282,7 +284,7 @@ __global__ void merge_insert_kernel(MergeInput in, Slot* table, uint64_t mask,
     else if (q < 16) hi |= (uint64_t)f << (8 * (q - 8));
   }
   uint64_t key = finish_key(h, key_mask);
-  WordId id = len <= 16 ? short_id(lo, hi, 0) : long_id(w, len, 0);
+  WordId id = len <= 16 && packable(lo, hi) ? short_id(lo, hi, 0) : long_id(w, len, 0);
   uint64_t slot = table_insert<false>(table, mask, key, id, c, hdr, occ_limit);
   if (joint && slot != ~0ull) add64(&joint[slot * C + in.column], c);
 }
@@ -323,35 +325,6 @@ hipError_t launch_hash_words(const uint8_t* bytes, const uint64_t* offsets, uint
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(hash_words_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s,
                      bytes, offsets, n, out);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------------------------------
-// per-document CSR from entry documents (entries already grouped by a stable sort)
-// ------------------------------------------------------------------------------------------
-__global__ void doc_ptr_kernel(const uint64_t* docs_sorted, const Header* hdr, uint64_t n_docs,
-                               uint64_t* doc_ptr) {
-  uint64_t n = hdr->n_entries;
-  uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (e > n) return;
-  uint64_t dprev = e == 0 ? 0 : docs_sorted[e - 1] + 1;  // first document starting here
-  uint64_t dcur = e == n ? n_docs : docs_sorted[e];        // last document starting here
-  for (uint64_t d = dprev; d <= dcur && d <= n_docs; ++d) doc_ptr[d] = e;
-}
-
-__global__ void doc_len_kernel(const uint64_t* doc_ptr, uint64_t n_docs, uint64_t* doc_len) {
-  uint64_t d = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (d < n_docs) doc_len[d] = doc_ptr[d + 1] - doc_ptr[d];
-}
-
-hipError_t launch_doc_csr(const uint64_t* docs_sorted, uint64_t n_entries_max, const Header* hdr,
-                          uint64_t n_docs, uint64_t* doc_ptr, uint64_t* doc_len, hipStream_t s) {
-  uint32_t grid = (uint32_t)((n_entries_max + 1 + 255) / 256);
-  hipLaunchKernelGGL(doc_ptr_kernel, dim3(grid), dim3(256), 0, s, docs_sorted, hdr, n_docs,
-                     doc_ptr);
-  if (n_docs)
-    hipLaunchKernelGGL(doc_len_kernel, dim3((uint32_t)((n_docs + 255) / 256)), dim3(256), 0, s,
-                       doc_ptr, n_docs, doc_len);
   return hipGetLastError();
 }
 
@@ -509,18 +482,103 @@ hipError_t launch_topk(const TopkParams& P, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------------------
-// hipcub wrappers (sort by document, scans)
 // ------------------------------------------------------------------------------------------
-hipError_t sort_pairs_u64(void* temp, size_t* temp_bytes, const uint64_t* keys_in,
-                          uint64_t* keys_out, const uint64_t* vals_in, uint64_t* vals_out,
-                          uint64_t n, int end_bit, hipStream_t s) {
-  return hipcub::DeviceRadixSort::SortPairs(temp, *temp_bytes, keys_in, keys_out, vals_in,
-                                            vals_out, (int)n, 0, end_bit, s);
+// exclusive prefix sum of uint64 values: per-block scans, a scan of the block totals, and
+// the block offsets added back
+// ------------------------------------------------------------------------------------------
+constexpr uint32_t kScanBlock = 256, kScanItems = 4, kScanSpan = kScanBlock * kScanItems;
+
+uint64_t excl_scan_scratch(uint64_t n) { return ((n + kScanSpan - 1) / kScanSpan + 1) * 8; }
+
+// out[i] = sum of in[b*span .. i) for the block b holding i; sums[b] = the block's total
+__global__ __launch_bounds__(kScanBlock) void scan_local_kernel(const uint64_t* in, uint64_t* out,
+                                                                uint64_t n, uint64_t* sums) {
+  __shared__ uint64_t s_tmp[kScanBlock / 64];
+  const uint64_t first = blockIdx.x * (uint64_t)kScanSpan + (uint64_t)threadIdx.x * kScanItems;
+  uint64_t v[kScanItems], t = 0;
+  for (uint32_t j = 0; j < kScanItems; ++j) {
+    v[j] = first + j < n ? in[first + j] : 0;
+    t += v[j];
+  }
+  uint64_t tot;
+  uint64_t e = block_excl_scan<kScanBlock>(t, s_tmp, &tot);
+  for (uint32_t j = 0; j < kScanItems; ++j) {
+    if (first + j < n) out[first + j] = e;
+    e += v[j];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-hipError_t excl_sum_u64(void* temp, size_t* temp_bytes, const uint64_t* in, uint64_t* out,
-                        uint64_t n, hipStream_t s) {
-  return hipcub::DeviceScan::ExclusiveSum(temp, *temp_bytes, in, out, (int)n, s);
+// sums[0 .. nb) becomes its exclusive scan (one workgroup)
+__global__ __launch_bounds__(1024) void scan_sums_kernel(uint64_t* sums, uint64_t nb) {
+  __shared__ uint64_t s_tmp[16];
+  __shared__ uint64_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint64_t base = 0; base < nb; base += 1024) {
+    const uint64_t i = base + threadIdx.x;
+    const uint64_t v = i < nb ? sums[i] : 0;
+    uint64_t tot;
+    const uint64_t e = block_excl_scan<1024>(v, s_tmp, &tot);
+    if (i < nb) sums[i] = e + s_carry;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += tot;
+    __syncthreads();
+  }
+}
+
+__global__ void scan_add_kernel(uint64_t* out, uint64_t n, const uint64_t* sums) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] += sums[i / kScanSpan];
+}
+
+hipError_t excl_scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* sums,
+                         hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t nb = (n + kScanSpan - 1) / kScanSpan;
+  hipLaunchKernelGGL(scan_local_kernel, dim3((uint32_t)nb), dim3(kScanBlock), 0, s, in, out, n,
+                     sums);
+  if (nb > 1) {
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, sums, nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, out,
+                       n, sums);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// entries grouped by document: a counting sort (histogram, scan, scatter); the order inside a
+// document is unspecified, as the result's entry order is
+// ------------------------------------------------------------------------------------------
+__global__ void doc_hist_kernel(const uint64_t* docs, uint64_t n, uint64_t* doc_len) {
+  const uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (e < n) atomicAdd((unsigned long long*)&doc_len[docs[e]], 1ull);
+}
+
+__global__ void doc_scatter_kernel(const uint64_t* docs, const uint64_t* slots, uint64_t n,
+                                   const uint64_t* doc_ptr, uint64_t* fill,
+                                   uint64_t* sorted_docs, uint64_t* sorted_slots) {
+  const uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const uint64_t d = docs[e];
+  const uint64_t at = doc_ptr[d] + atomicAdd((unsigned long long*)&fill[d], 1ull);
+  sorted_docs[at] = d;
+  sorted_slots[at] = slots[e];
+}
+
+hipError_t group_by_doc(const uint64_t* docs, const uint64_t* slots, uint64_t n, uint64_t n_docs,
+                        uint64_t* doc_ptr, uint64_t* doc_len, uint64_t* fill, uint64_t* sums,
+                        uint64_t* sorted_docs, uint64_t* sorted_slots, hipStream_t s) {
+  hipError_t e = launch_fill_zero(doc_len, n_docs * 8, s);
+  if (e == hipSuccess) e = launch_fill_zero(fill, n_docs * 8, s);
+  if (e != hipSuccess || n_docs == 0) return e;
+  const uint32_t grid = (uint32_t)((n + 255) / 256);
+  if (n) hipLaunchKernelGGL(doc_hist_kernel, dim3(grid), dim3(256), 0, s, docs, n, doc_len);
+  e = excl_scan_u64(doc_len, doc_ptr, n_docs, sums, s);
+  if (e == hipSuccess && n)
+    hipLaunchKernelGGL(doc_scatter_kernel, dim3(grid), dim3(256), 0, s, docs, slots, n, doc_ptr,
+                       fill, sorted_docs, sorted_slots);
+  return e == hipSuccess ? hipGetLastError() : e;
 }
 
 }  // namespace wc

@@ -200,8 +200,12 @@ class Corpus:
 
 
 def gen_docs(sizes, vocab, vlens, probs, seed: int, device="cpu", per_doc_truth=False,
-             max_tokens_per_pass: int = 1 << 25) -> Corpus:
-    """Documents of the given byte sizes, filled with Zipf tokens and padded with spaces."""
+             max_tokens_per_pass: int = 1 << 25, pair_truth=False) -> Corpus:
+    """Documents of the given byte sizes, filled with Zipf tokens and padded with spaces.
+
+    pair_truth: also return, in extra["pair_keys"] / extra["pair_counts"], the sorted distinct
+    keys document * N + rank of the drawn tokens and how often each was drawn (the exact
+    per-document tables, for corpora too large for one histogram per document)."""
     device = torch.device(device)
     sizes = np.asarray(sizes, dtype=np.int64)
     n_docs = len(sizes)
@@ -216,6 +220,7 @@ def gen_docs(sizes, vocab, vlens, probs, seed: int, device="cpu", per_doc_truth=
     budget = np.minimum(budget, sizes // 2 + 1)
     expected = torch.zeros(dr.n, dtype=torch.int64, device=device)
     doc_truth = [] if per_doc_truth else None
+    pair_keys, pair_counts = [], []
     n_tok = 0
     d0 = 0
     while d0 < n_docs:
@@ -252,10 +257,21 @@ def gen_docs(sizes, vocab, vlens, probs, seed: int, device="cpu", per_doc_truth=
             dk = doc_of[keep]
             for j in range(d1 - d0):
                 doc_truth.append(torch.bincount(rk[dk == j], minlength=dr.n).cpu())
+        if pair_truth:
+            # documents of one pass never appear in another, so the keys stay sorted overall
+            u, n_u = torch.unique((doc_of[keep] + d0) * dr.n + rk, return_counts=True)
+            pair_keys.append(u)
+            pair_counts.append(n_u)
         n_tok += int(keep.sum())
         d0 = d1
-    return Corpus(text, torch.from_numpy(offsets).to(device), expected, vocab, vlens, n_tok,
-                  doc_truth)
+    cor = Corpus(text, torch.from_numpy(offsets).to(device), expected, vocab, vlens, n_tok,
+                 doc_truth)
+    if pair_truth:
+        cor.extra["pair_keys"] = torch.cat(pair_keys) if pair_keys else \
+            torch.empty(0, dtype=torch.int64, device=device)
+        cor.extra["pair_counts"] = torch.cat(pair_counts) if pair_counts else \
+            torch.empty(0, dtype=torch.int64, device=device)
+    return cor
 
 
 def gen_stream(size: int, vocab, vlens, probs, seed: int, device="cpu",
@@ -299,7 +315,8 @@ def doc_sizes(w: Workload, scale: float = 1.0) -> np.ndarray:
     return np.full(n, size, dtype=np.int64)
 
 
-def generate(name: str, device="cpu", scale: float = 1.0, per_doc_truth=False, progress=None):
+def generate(name: str, device="cpu", scale: float = 1.0, per_doc_truth=False, progress=None,
+             pair_truth=False):
     """Generate a named workload. scale < 1 shrinks the document count (or the stream size).
 
     Returns a Corpus, or for "corpora" workloads a list of one Corpus per corpus.
@@ -324,7 +341,8 @@ def generate(name: str, device="cpu", scale: float = 1.0, per_doc_truth=False, p
         return out
     sizes = doc_sizes(w, scale)
     probs = zipf_probs(w.vocab, w.zipf_s)
-    return gen_docs(sizes, vocab, vlens, probs, w.seed + 1, device, per_doc_truth)
+    return gen_docs(sizes, vocab, vlens, probs, w.seed + 1, device, per_doc_truth,
+                    pair_truth=pair_truth)
 
 
 def random_text(n_bytes: int, seed: int, alphabet: bytes = b"aZ0' ,\x80\n") -> bytes:

@@ -24,6 +24,7 @@ WC_GLOBAL, WC_PER_DOC = 0, 1
 WC_FLUSH_ALL, WC_FLUSH_BYPASS = 0, 1
 WC_DEBUG_TIME, WC_DEBUG_NO_LDS, WC_DEBUG_DIRECT, WC_DEBUG_SPILL, WC_DEBUG_DOCS = 1, 2, 4, 8, 16
 WC_FOLD_SQRT, WC_FOLD_ALT_HARMONIC = 0, 1
+WC_TOKENIZE_ASCII, WC_TOKENIZE_UTF8 = 0, 1
 
 
 class WcError(RuntimeError):
@@ -45,7 +46,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("count_bytes", ctypes.c_uint32), ("mode", ctypes.c_uint32),
                 ("table_slots", ctypes.c_uint64), ("tuning", ctypes.POINTER(Tuning)),
                 ("debug_flags", ctypes.c_uint32), ("debug_hash_bits", ctypes.c_uint32),
-                ("word_bytes_cap", ctypes.c_uint64)]
+                ("word_bytes_cap", ctypes.c_uint64), ("debug_count_bias", ctypes.c_uint64),
+                ("tokenizer", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Plan(ctypes.Structure):
@@ -61,7 +63,8 @@ class Result(ctypes.Structure):
                 ("d_words", ctypes.c_void_p), ("d_counts", ctypes.c_void_p),
                 ("d_doc_ptr", ctypes.c_void_p), ("d_doc_len", ctypes.c_void_p),
                 ("d_docs", ctypes.c_void_p),
-                ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
+                ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
+                ("stats", ctypes.c_uint64 * 5)]
 
 
 class TopKStruct(ctypes.Structure):
@@ -90,6 +93,15 @@ def lib():
         L.wc_count_plan.argtypes = [u64, u64, ctypes.POINTER(Opts), ctypes.POINTER(Plan)]
         L.wc_count.argtypes = [vp, u64, vp, u64, ctypes.POINTER(Opts), vp, u64,
                                ctypes.POINTER(Result), vp]
+        L.wc_count_host_plan.argtypes = [u64, u64, ctypes.POINTER(Opts), u64, ctypes.POINTER(Plan)]
+        L.wc_count_host.argtypes = [vp, u64, vp, u64, ctypes.POINTER(Opts), u64, vp, vp, u64,
+                                    ctypes.POINTER(Result), vp]
+        L.wc_sort_canonical.argtypes = [u64, vp, vp, vp, vp]
+        L.wc_sort_canonical.restype = ctypes.c_int32
+        L.wc_merge_dense_plan.argtypes = [ctypes.POINTER(Result), ctypes.POINTER(Opts), u64,
+                                          ctypes.POINTER(u64)]
+        L.wc_merge_dense.argtypes = [ctypes.POINTER(Result), ctypes.POINTER(Opts), vp, u64,
+                                     ctypes.POINTER(Result), vp]
         L.wc_merge_plan.argtypes = [ctypes.POINTER(ctypes.POINTER(Result)), u32,
                                     ctypes.POINTER(Opts), ctypes.POINTER(Plan)]
         L.wc_merge.argtypes = [ctypes.POINTER(ctypes.POINTER(Result)), u32, ctypes.POINTER(Opts),
@@ -134,7 +146,9 @@ def lib():
         L.wc_batch_destroy.argtypes = [vp]
         for f in ("wc_batch_plan", "wc_batch_create", "wc_batch_run", "wc_batch_destroy"):
             getattr(L, f).restype = ctypes.c_int32
-        for f in ("wc_count_plan", "wc_count", "wc_merge_plan", "wc_merge", "wc_topk_ratio_plan",
+        for f in ("wc_count_plan", "wc_count", "wc_count_host_plan",
+                  "wc_count_host", "wc_merge_dense_plan",
+                  "wc_merge_dense", "wc_merge_plan", "wc_merge", "wc_topk_ratio_plan",
                   "wc_topk_ratio", "wc_hash_words"):
             getattr(L, f).restype = ctypes.c_int32
         _lib = L
@@ -181,6 +195,13 @@ class Table:
     def total_tokens(self) -> int:
         return int(self.res.total_tokens)
 
+    @property
+    def stats(self) -> dict:
+        """Per-call statistics of the two-pass global count (all zero on other paths)."""
+        s = self.res.stats
+        return {"spilled": int(s[0]), "arena_direct": int(s[1]), "dict_words": int(s[2]),
+                "ring_waits": int(s[3]), "reduce_overflow": int(s[4])}
+
     def word_offsets(self) -> torch.Tensor:
         return self._view(self.res.d_word_offsets, 8 * (self.n_entries + 1), torch.int64)
 
@@ -225,7 +246,7 @@ class Table:
 
 
 def _opts(count_bytes, per_doc, table_slots, tuning, debug_flags, debug_hash_bits,
-          word_bytes_cap):
+          word_bytes_cap, debug_count_bias=0, utf8=False):
     o = Opts()
     o.count_bytes = count_bytes
     o.mode = WC_PER_DOC if per_doc else WC_GLOBAL
@@ -234,6 +255,8 @@ def _opts(count_bytes, per_doc, table_slots, tuning, debug_flags, debug_hash_bit
     o.debug_flags = debug_flags
     o.debug_hash_bits = debug_hash_bits
     o.word_bytes_cap = word_bytes_cap
+    o.debug_count_bias = debug_count_bias
+    o.tokenizer = WC_TOKENIZE_UTF8 if utf8 else WC_TOKENIZE_ASCII
     return o
 
 
@@ -255,7 +278,8 @@ def count_plan(corpus_len: int, n_docs: int, *, count_bytes=8, per_doc=False, ta
 def count(corpus: torch.Tensor, offsets: Optional[torch.Tensor] = None, *, count_bytes: int = 8,
           per_doc: bool = False, table_slots: int = 0, tuning: Optional[Tuning] = None,
           debug_flags: int = 0, debug_hash_bits: int = 0, word_bytes_cap: int = 0,
-          stream=None, regrow: bool = True, workspace: Optional[torch.Tensor] = None) -> Table:
+          stream=None, regrow: bool = True, workspace: Optional[torch.Tensor] = None,
+          debug_count_bias: int = 0, utf8: bool = False) -> Table:
     """Count the words of a device corpus (uint8) split into documents by offsets (int64).
 
     On a full table the call is repeated with twice the slots (regrow=True), and on an
@@ -275,7 +299,7 @@ def count(corpus: torch.Tensor, offsets: Optional[torch.Tensor] = None, *, count
         raise ValueError("offsets must hold at least one value")
     while True:
         o = _opts(count_bytes, per_doc, table_slots, tuning, debug_flags, debug_hash_bits,
-                  word_bytes_cap)
+                  word_bytes_cap, debug_count_bias, utf8)
         p = Plan()
         st = lib().wc_count_plan(n, n_docs, ctypes.byref(o), ctypes.byref(p))
         if st != WC_OK:
@@ -310,6 +334,61 @@ def count(corpus: torch.Tensor, offsets: Optional[torch.Tensor] = None, *, count
         return Table(res, ws)
 
 
+def count_host(text, offsets=None, *, piece_bytes: int = 256 << 20, count_bytes: int = 8,
+               table_slots: int = 0, tuning: Optional[Tuning] = None, debug_flags: int = 0,
+               utf8: bool = False, device="cuda", stream=None, regrow: bool = True,
+               d_text: Optional[torch.Tensor] = None) -> Table:
+    """Count a host corpus (numpy uint8 array, bytes, or a CPU uint8 tensor, ideally pinned)
+    through wc_count_host: pieces are copied to the device while earlier pieces are counted.
+    The device copy of the text (d_text, allocated when not given) is kept with the result."""
+    if isinstance(text, torch.Tensor):
+        if text.is_cuda or text.dtype != torch.uint8 or not text.is_contiguous():
+            raise ValueError("text must be a contiguous host uint8 tensor")
+        host_ptr, n, keep_host = text.data_ptr(), text.numel(), text
+    else:
+        buf = np.frombuffer(bytes(text), dtype=np.uint8) if isinstance(text, (bytes, bytearray)) \
+            else np.ascontiguousarray(text, dtype=np.uint8)
+        keep_host = buf if len(buf) else np.zeros(1, np.uint8)
+        host_ptr, n = keep_host.ctypes.data, len(buf)
+    off = np.ascontiguousarray([0, n] if offsets is None else offsets, dtype=np.uint64)
+    n_docs = len(off) - 1
+    if d_text is None:
+        d_text = torch.empty(max(n, 1), dtype=torch.uint8, device=device)
+    while True:
+        o = _opts(count_bytes, False, table_slots, tuning, debug_flags, 0, 0, 0, utf8)
+        p = Plan()
+        st = lib().wc_count_host_plan(n, n_docs, ctypes.byref(o), piece_bytes, ctypes.byref(p))
+        if st != WC_OK:
+            raise WcError(st, "wc_count_host_plan")
+        ws = _alloc(p.workspace_bytes, d_text.device)
+        res = Result()
+        st = lib().wc_count_host(ctypes.c_void_p(host_ptr), n, off.ctypes.data_as(ctypes.c_void_p),
+                                 n_docs, ctypes.byref(o), piece_bytes,
+                                 ctypes.c_void_p(d_text.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel(), ctypes.byref(res), _stream_handle(stream))
+        if st == WC_ETABLEFULL and regrow:
+            table_slots = 2 * int(p.table_slots)
+            continue
+        if st != WC_OK:
+            raise WcError(st, "wc_count_host")
+        return Table(res, ws, keep=(d_text, keep_host))
+
+
+def sort_canonical(words: np.ndarray, word_offsets: np.ndarray, docs=None) -> np.ndarray:
+    """wc_sort_canonical: the permutation that orders a host table by (document, word)."""
+    o = np.ascontiguousarray(word_offsets, dtype=np.uint64)
+    n = len(o) - 1
+    w = np.ascontiguousarray(words, dtype=np.uint8)
+    w = w if len(w) else np.zeros(1, np.uint8)
+    d = None if docs is None else np.ascontiguousarray(docs, dtype=np.uint64)
+    perm = np.zeros(max(n, 1), dtype=np.uint64)
+    st = lib().wc_sort_canonical(n, o.ctypes.data, w.ctypes.data,
+                                 d.ctypes.data if d is not None else None, perm.ctypes.data)
+    if st != WC_OK:
+        raise WcError(st, "wc_sort_canonical")
+    return perm[:n].astype(np.int64)
+
+
 def _result_array(tables: Sequence[Table]):
     arr = (ctypes.POINTER(Result) * len(tables))(*[ctypes.pointer(t.res) for t in tables])
     return arr
@@ -338,6 +417,37 @@ def merge(tables: Sequence[Table], *, count_bytes: int = 8, table_slots: int = 0
         if st != WC_OK:
             raise WcError(st, "wc_merge")
         return Table(res, ws)
+
+
+def merge_dense(per_doc: Table, *, count_bytes: int = 8, stream=None, debug_flags: int = 0,
+                debug_count_bias: int = 0) -> Table:
+    """The paper's reduce: per-document counts as a zero-padded words x documents matrix,
+    summed by rows (wc_merge_dense). The result equals merge([per_doc])."""
+    if per_doc.docs() is None:
+        raise ValueError("merge_dense needs a per-document table")
+    dev = per_doc.workspace.device
+    n, d = per_doc.n_entries, max(int(per_doc.res.n_docs), 1)
+    # plan for the upper bound when that matrix is small; else learn the rows first
+    rows = n if n * d * 4 <= (1 << 30) else 1
+    o = _opts(count_bytes, False, 0, None, debug_flags, 0, 0, debug_count_bias)
+    for _ in range(2):
+        need = ctypes.c_uint64()
+        st = lib().wc_merge_dense_plan(ctypes.byref(per_doc.res), ctypes.byref(o), rows,
+                                       ctypes.byref(need))
+        if st != WC_OK:
+            raise WcError(st, "wc_merge_dense_plan")
+        ws = _alloc(need.value, dev)
+        res = Result()
+        st = lib().wc_merge_dense(ctypes.byref(per_doc.res), ctypes.byref(o),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(res),
+                                  _stream_handle(stream))
+        if st == WC_ENOMEM and res.n_entries > rows:
+            rows = int(res.n_entries)
+            continue
+        if st != WC_OK:
+            raise WcError(st, "wc_merge_dense")
+        return Table(res, ws)
+    raise WcError(WC_ENOMEM, "wc_merge_dense")
 
 
 @dataclass

@@ -80,3 +80,21 @@ def test_fold_sum_argument_errors_without_gpu():
     assert L.wc_fold_sum(0, (1 << 53) + 1, p, p, 1 << 20, None) == wc.WC_EINVAL
     assert L.wc_fold_sum(0, 10 ** 8, p, p, 8, None) == wc.WC_EINVAL
     assert L.wc_fold_sum(0, 10, None, p, 1 << 20, None) == wc.WC_EINVAL
+
+
+def test_sort_canonical_without_gpu():
+    """The host helper orders a table by (document, word bytes), a proper prefix first, for
+    stored offsets that do not start at 0."""
+    import numpy as np
+    rng = np.random.default_rng(3)
+    words = [bytes(rng.choice(np.frombuffer(b"ab'\xc3\xa9z", np.uint8), rng.integers(1, 5)))
+             for _ in range(400)]
+    docs = rng.integers(0, 5, size=len(words))
+    blob = b"".join(words)
+    off = np.concatenate([[0], np.cumsum([len(w) for w in words])]) + 1000
+    perm = wc.sort_canonical(np.frombuffer(blob, np.uint8), off, docs)
+    want = sorted(range(len(words)), key=lambda e: (int(docs[e]), words[e], e))
+    assert list(perm) == want
+    perm = wc.sort_canonical(np.frombuffer(blob, np.uint8), off)
+    assert [words[e] for e in perm] == sorted(words)
+    assert len(wc.sort_canonical(np.zeros(0, np.uint8), np.zeros(1, np.uint64))) == 0

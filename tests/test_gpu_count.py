@@ -175,27 +175,62 @@ def test_invalid_offsets_raise():
     assert e.value.status == wc.WC_EINVAL
 
 
-@pytest.mark.parametrize("path", ["direct", "spill"])
-@pytest.mark.parametrize("stage", [4096, 8192])
+WORD_BYTES = np.frombuffer(b"abcXYZ019'", np.uint8)
+SEP_BYTES = np.frombuffer(b" ,\n.", np.uint8)
+
+
+def straddling_words(edge: int, n_edges: int, seed: int, max_len: int = 40) -> bytes:
+    """Text in which, for every (length L in 1..max_len, offset k in 0..L), one word of L bytes
+    covers the k bytes before some multiple of `edge` and the L - k bytes from it (k = 0: the
+    word starts on the edge; k = L: it ends just before it). The gaps are filled with random
+    short words and separators."""
+    rng = np.random.default_rng(seed)
+    cases = [(L, k) for L in range(1, max_len + 1) for k in range(L + 1)]
+    order = rng.permutation(len(cases))
+    out = bytearray()
+    for i in range(n_edges):
+        L, k = cases[order[i % len(cases)]]
+        start = (i + 1) * edge - k
+        # filler up to start - 1, then one separator before the word
+        while len(out) < start - 1:
+            room = start - 1 - len(out)
+            fl = int(rng.integers(1, 8))
+            if room > fl + 1:
+                out += rng.choice(WORD_BYTES, fl).tobytes() + rng.choice(SEP_BYTES, 1).tobytes()
+            else:
+                out += b" " * room
+        out += rng.choice(SEP_BYTES, 1).tobytes()
+        assert len(out) == start
+        out += rng.choice(WORD_BYTES, L).tobytes() + rng.choice(SEP_BYTES, 1).tobytes()
+    return bytes(out)
+
+
+def check_lengths_span(text: bytes, offsets, lo: int, hi: int):
+    """The input really holds words of every length lo..hi (guards the test's own input)."""
+    lens = {len(w) for w in oracle.count(text, offsets).as_dict()}
+    missing = set(range(lo, hi + 1)) - lens
+    assert not missing, f"input has no words of lengths {sorted(missing)}"
+
+
+@pytest.mark.parametrize("stage,path", [(4096, "direct"), (8192, "direct"), (1024, "spill")])
 def test_words_across_stage_boundaries(stage, path):
-    # words of every length 1..40 ending and starting at every position near stage edges
-    rng = np.random.default_rng(stage)
-    parts = []
-    pos = 0
-    while pos < 5 * stage:
-        L = int(rng.integers(1, 41))
-        w = bytes(rng.choice(list(b"abcXYZ019'"), L))
-        sep = bytes(rng.choice(list(b" ,\n."), int(rng.integers(1, 3))))
-        parts.append(w + sep)
-        pos += L + len(sep)
-    text = b"".join(parts)
-    if path == "spill" and stage != 8192:
-        pytest.skip("the two-pass kernel has one stage size (16 KiB, 1 KiB per wave)")
+    """Words of every length 1..40 at every offset across stripe / stage edges: the one-pass
+    kernel's stages (4 or 8 KiB) and the two-pass kernel's 1 KiB stripes (16 KiB stages; one
+    stripe per wave), so words longer than 16 bytes and words carried into the next stripe both
+    occur at edges."""
+    n_edges = 861 if stage == 1024 else 200
+    text = straddling_words(stage, n_edges, stage)
+    check_lengths_span(text, None, 1, 40)
+    tu = wc.make_tuning(stage_bytes=stage) if path == "direct" else None
     for shift in (0, 1, 7, 15):
         t = b"q" * shift + text
-        tu = wc.make_tuning(stage_bytes=stage)
+        say("stage", stage, path, "shift", shift, "bytes", len(t))
         check(t, tuning=tu, debug_flags=PATHS[path])
         check(t, [0, shift, len(t) // 3, len(t)], tuning=tu, debug_flags=PATHS[path])
+    if path == "spill":
+        # one workgroup over the whole text: the carried word crosses stages inside one range
+        check(text, tuning=wc.make_tuning(grid_blocks=1), debug_flags=PATHS[path])
+        check(text, tuning=wc.make_tuning(grid_blocks=3), debug_flags=PATHS[path])
 
 
 def test_misaligned_corpus_pointer():
@@ -250,6 +285,57 @@ def test_table_regrow():
     with pytest.raises(wc.WcError) as e:
         gpu_count(text, table_slots=64, regrow=False)
     assert e.value.status == wc.WC_ETABLEFULL
+
+
+OVERFLOW_MODES = {
+    "direct": dict(debug_flags=wc.WC_DEBUG_DIRECT),
+    "spill": dict(debug_flags=wc.WC_DEBUG_SPILL),
+    "docs": dict(per_doc=True, debug_flags=wc.WC_DEBUG_DOCS),
+    "per_doc_direct": dict(per_doc=True, debug_flags=wc.WC_DEBUG_DIRECT),
+}
+
+
+@pytest.mark.parametrize("mode", list(OVERFLOW_MODES))
+def test_count_width_overflow(mode):
+    """A count above INT32_MAX exported at 4 bytes is WC_EOVERFLOW on every export path (the
+    global one- and two-pass paths, both per-document kernels); at exactly INT32_MAX it is not;
+    at 8 bytes the wide value is exported as is. The debug bias added to every exported count
+    stands in for 2^31 tokens."""
+    kw = OVERFLOW_MODES[mode]
+    text = b"the cat The dog, the " * 2000
+    off = [0, len(text) // 2, len(text)]
+    want = oracle.count(text, off, per_doc=kw.get("per_doc", False)).as_dict()
+    top = max(want.values())
+    i32 = (1 << 31) - 1
+    # the largest count lands exactly on INT32_MAX: still fits
+    got = check_biased(text, off, i32 - top, 4, kw, want)
+    assert max(got.values()) == i32
+    with pytest.raises(wc.WcError) as e:
+        gpu_count(text, off, count_bytes=4, debug_count_bias=i32 - top + 1, **kw)
+    assert e.value.status == wc.WC_EOVERFLOW
+    check_biased(text, off, 3 << 33, 8, kw, want)
+
+
+def check_biased(text, off, bias, count_bytes, kw, want):
+    got = gpu_count(text, off, count_bytes=count_bytes, debug_count_bias=bias, **kw)
+    assert got.total_tokens == sum(want.values())
+    d = got.as_dict()
+    assert d == {k: v + bias for k, v in want.items()}
+    return d
+
+
+def test_merge_width_overflow():
+    """Two wide tables whose sums pass INT32_MAX: merging them at 4 bytes is WC_EOVERFLOW, at 8
+    bytes the exact sums."""
+    text = b"alpha beta alpha gamma " * 500
+    want = oracle.count(text).as_dict()
+    big = 3 << 29  # 1.5 * 2^30: one table fits int32, the sum of two does not
+    t = gpu_count(text, count_bytes=8, debug_count_bias=big)
+    assert wc.merge([t, t], count_bytes=8).as_dict() == {k: 2 * (v + big) for k, v in want.items()}
+    with pytest.raises(wc.WcError) as e:
+        wc.merge([t, t], count_bytes=4)
+    assert e.value.status == wc.WC_EOVERFLOW
+    assert wc.merge([t], count_bytes=4).as_dict() == {k: v + big for k, v in want.items()}
 
 
 def test_word_capacity_regrow():
@@ -344,35 +430,51 @@ def test_spill_heavy_counts():
     check(text, tuning=wc.make_tuning(grid_blocks=1), debug_flags=wc.WC_DEBUG_SPILL)
 
 
-def _part_of(word: bytes) -> int:
-    """Partition of a short word in the two-pass kernels (their 32-bit word hash, low 8 bits);
-    used only to build inputs that crowd one partition."""
-    b = word.lower().ljust(16, b"\0")
-    a, b_, c, d = (int.from_bytes(b[i:i + 4], "little") for i in (0, 4, 8, 12))
-    m = 0xffffffff
-    h = ((a * 0x9E3779B1) ^ (b_ * 0x85EBCA77) ^ (c * 0xC2B2AE3D) ^ (d * 0x27D4EB2F)) & m
-    h ^= h >> 15
-    h = (h * 0x2C1B3C6D) & m
-    h ^= h >> 13
-    return h & 255
+def _parts_of(words: np.ndarray) -> np.ndarray:
+    """Partitions of words of at most 16 lower-case bytes (uint8[n, 16], zero padded) in the
+    two-pass kernels: the low 8 bits of their 32-bit word hash (the packed word's dwords folded
+    with rotations, then the MurmurHash3 finaliser). Used only to build inputs that crowd one
+    partition; the test also checks the kernel's own statistics, so a change of the kernel's
+    hash cannot leave it hollow."""
+    d = np.ascontiguousarray(words).view("<u4").astype(np.uint64)
+    a, b, c, e = d[:, 0], d[:, 1], d[:, 2], d[:, 3]
+    m = np.uint64(0xffffffff)
+    rotr = lambda x, r: ((x >> np.uint64(r)) | (x << np.uint64(32 - r))) & m
+    h = ((a ^ rotr(b, 21)) + (c ^ rotr(e, 13))) & m
+    h ^= h >> np.uint64(16)
+    h = (h * np.uint64(0x85EBCA6B)) & m
+    h ^= h >> np.uint64(13)
+    h = (h * np.uint64(0xC2B2AE35)) & m
+    h ^= h >> np.uint64(16)
+    return (h & np.uint64(255)).astype(np.int64)
 
 
 def test_two_pass_crowded_partition():
-    """Thousands of distinct words of one partition in every stage: the LDS staging of that
-    partition fills, the overflow list fills, and the rest goes to the global table."""
+    """Thousands of distinct words of one partition: its LDS ring stays full (tokens wait for
+    a slot and chunks for their turn), and with one or three pass-1 workgroups its arena region
+    (a few 4 KiB blocks) is used up, so the remaining records go straight to the global
+    table."""
     rng = np.random.default_rng(11)
-    words = set()
-    while len(words) < 6000:
-        w = bytes(rng.choice(list(b"abcdefghijklmnopqrstuvwxyz"), int(rng.integers(3, 9))))
-        if _part_of(w) == 0:
-            words.add(w)
-    words = sorted(words)
-    seq = [words[i] for i in rng.permutation(np.repeat(np.arange(len(words)), 2))]
+    cand = rng.integers(ord("a"), ord("z") + 1, size=(2_000_000, 16), dtype=np.uint8)
+    lens = rng.integers(3, 13, size=len(cand))
+    cand[np.arange(16)[None, :] >= lens[:, None]] = 0
+    keep = cand[_parts_of(cand) == 0]
+    words = sorted({bytes(r[r != 0]) for r in keep})[:6000]
+    assert len(words) == 6000
+    seq = [words[i] for i in rng.permutation(np.repeat(np.arange(len(words)), 3))]
     text = b" ".join(seq)
+    assert len({len(w) for w in words}) == 10
     for lds in (256, 4096):
-        check(text, tuning=wc.make_tuning(lds_entries=lds), debug_flags=wc.WC_DEBUG_SPILL)
-    check(text, [0, len(text) // 2, len(text)], tuning=wc.make_tuning(grid_blocks=1),
-          debug_flags=wc.WC_DEBUG_SPILL)
+        got = check(text, tuning=wc.make_tuning(lds_entries=lds), debug_flags=wc.WC_DEBUG_SPILL)
+        say("lds", lds, got.stats)
+        assert got.stats["spilled"] > 0.9 * len(seq) - lds * 3
+        assert got.stats["ring_waits"] > 0
+    for grid in (1, 3):
+        got = check(text, [0, len(text) // 2, len(text)], tuning=wc.make_tuning(grid_blocks=grid),
+                    debug_flags=wc.WC_DEBUG_SPILL)
+        say("grid", grid, got.stats)
+        assert got.stats["arena_direct"] > 0
+        assert got.stats["ring_waits"] > 0
 
 
 def test_two_pass_document_edges():
@@ -449,6 +551,91 @@ def test_stream_full_size_against_rank_histogram():
     torch.cuda.empty_cache()
 
 
+def vocab_keys(words: torch.Tensor, offsets: torch.Tensor, max_len: int) -> torch.Tensor:
+    """Base-32 key of each word of at most max_len bytes over 'a'..'z' (a = 1, no byte = 0),
+    from a word-bytes array and its offsets[n + 1] (torch, any device): distinct words have
+    distinct keys, so a key identifies a vocabulary word."""
+    lens = offsets[1:] - offsets[:-1]
+    assert int(lens.max()) <= max_len and int(lens.min()) >= 1
+    key = torch.zeros(lens.numel(), dtype=torch.int64, device=words.device)
+    last = max(words.numel() - 1, 0)
+    for j in range(max_len):
+        b = words[(offsets[:-1] + j).clamp(max=last)].long() - 96
+        key = key * 32 + torch.where(j < lens, b, torch.zeros_like(b))
+    return key
+
+
+def ranks_of(table_words, table_offsets, vocab: np.ndarray, vlens: np.ndarray, dev):
+    """Vocabulary rank of each exported word (every word must be a vocabulary word)."""
+    L = vocab.shape[1]
+    vo = np.zeros(len(vlens) + 1, dtype=np.int64)
+    np.cumsum(vlens, out=vo[1:])
+    vw = np.concatenate([vocab[k, :vlens[k]] for k in range(len(vlens))])
+    vk = vocab_keys(torch.from_numpy(vw).to(dev), torch.from_numpy(vo).to(dev), L)
+    sk, perm = torch.sort(vk)
+    tk = vocab_keys(table_words, table_offsets, L)
+    i = torch.searchsorted(sk, tk).clamp(max=sk.numel() - 1)
+    assert torch.equal(sk[i], tk), "an exported word is not a vocabulary word"
+    return perm[i]
+
+
+def test_batched_full_size_against_pair_histograms():
+    """batched-100k at its full size (100,000 documents, 2.7 GB, 200,000-word vocabulary): one
+    captured-graph run of the batch API gives every (document, word) count the generator drew,
+    and its CSR layout is consistent."""
+    say("generating batched-100k with per-(document, word) truth")
+    c = synth.generate("batched-100k", device=DEV, pair_truth=True)
+    n_docs = c.offsets.numel() - 1
+    say("docs", n_docs, "bytes", c.text.numel(), "tokens", c.n_tokens)
+    b = wc.Batch(max_docs=n_docs, max_bytes=c.text.numel(), count_bytes=4,
+                 **wc.output_sizes(c.text, c.offsets, count_bytes=4))
+    for rep in range(2):  # capture, then replay
+        got = b.run(c.text, c.offsets)
+        assert got.total_tokens == c.n_tokens
+        n = got.n_entries
+        assert n == c.extra["pair_keys"].numel()
+        rank = ranks_of(got.words(), got.word_offsets(), c.vocab, c.vocab_lens, DEV)
+        docs = got.docs()
+        keys = docs * len(c.vocab_lens) + rank
+        order = torch.argsort(keys)
+        assert torch.equal(keys[order], c.extra["pair_keys"])
+        assert torch.equal(got.counts().long()[order], c.extra["pair_counts"])
+        # CSR: document d's entries are the doc_len[d] entries from doc_ptr[d]
+        dp, dl = got.doc_ptr(), got.doc_len()
+        assert int(dl.sum()) == n
+        base = torch.repeat_interleave(dp, dl)
+        first = torch.repeat_interleave(torch.cumsum(dl, 0) - dl, dl)
+        pos = base + torch.arange(n, device=DEV) - first
+        assert torch.equal(torch.sort(pos).values, torch.arange(n, device=DEV))
+        assert torch.equal(docs[pos], torch.repeat_interleave(torch.arange(n_docs, device=DEV), dl))
+        say("rep", rep, "entries", n, "ok")
+        del rank, docs, keys, order, base, first, pos
+    b.close()
+    del c
+    torch.cuda.empty_cache()
+
+
+def test_corpora_full_size_counts_and_top50():
+    """corpora-4x2000 at its full size (4 corpora x 2,000 documents, ~80 MB): each corpus's
+    table and the top-50 distinctive words per corpus equal the oracle's."""
+    cs = synth.generate("corpora-4x2000")
+    tabs, otabs = [], []
+    for i, c in enumerate(cs):
+        say("corpus", i, "bytes", c.text.numel())
+        got = check(c.text.numpy(), c.offsets.numpy(), count_bytes=4)
+        assert got.as_dict() == c.expected_table()
+        tabs.append(got)
+        otabs.append(oracle.count(c.text.numpy(), c.offsets.numpy()))
+    got = wc.topk_ratio(tabs, 50, 1)
+    want = oracle.topk_ratio(otabs, 50, 1)
+    assert got.vocab_size == want.vocab_size
+    for i in range(len(cs)):
+        assert got.words[i] == want.words[i]
+        assert list(got.n_c[i]) == list(map(int, want.n_c[i]))
+        assert list(got.n_rest[i]) == list(map(int, want.n_rest[i]))
+        np.testing.assert_allclose(got.score[i], want.score[i], rtol=1e-12)
+
+
 # ------------------------------------------------------------------------------------------
 # merge, top-k, hash
 # ------------------------------------------------------------------------------------------
@@ -469,6 +656,37 @@ def test_merge_matches_oracle():
         t = b" ".join(w.encode() for w, n in p.items() for _ in range(n))
         parts.append(gpu_count(t))
     assert {k.decode(): v for k, v in wc.merge(parts).as_dict().items()} == g["reduced"]
+
+
+def test_dense_reduce_matches_merge_and_oracle():
+    """The paper's zero-padded words x documents matrix summed by rows (Section 3.3) gives
+    the oracle's reduced table, as the hash merge does: a few documents (one thread per row),
+    hundreds of documents (one wave per row), empty documents, long words."""
+    g = golden("section3_3_grouping.json")
+    w = g["word"].encode()
+    text, off = join_docs([b" ".join([w] * n) + b"." for n in g["per_doc"]])
+    per = gpu_count(text, off, per_doc=True)
+    assert wc.merge_dense(per).as_dict() == {w: g["reduced"]}
+    c = synth.generate("plain-1MB")
+    cs = synth.generate("corpora-4x2000", scale=0.1)
+    long = b" ".join([b"Q" * 40, b"q" * 40, b"a" * 17, b"b"])
+    cases = [(c.text.numpy(), c.offsets.numpy()),
+             (cs[0].text.numpy(), cs[0].offsets.numpy()),
+             (np.frombuffer(long * 3, np.uint8), [0, 0, len(long), len(long), 3 * len(long)])]
+    for text, off in cases:
+        per = gpu_count(text, off, per_doc=True, count_bytes=4)
+        want = oracle.count(text, off).as_dict()
+        for cb in (4, 8):
+            got = wc.merge_dense(per, count_bytes=cb)
+            assert got.as_dict() == want
+            assert got.total_tokens == sum(want.values())
+        assert wc.merge([per]).as_dict() == want
+    # the row sums are checked against the count width
+    per = gpu_count(cases[0][0], cases[0][1], per_doc=True, count_bytes=8,
+                    debug_count_bias=1 << 30)
+    with pytest.raises(wc.WcError) as e:
+        wc.merge_dense(per, count_bytes=4)   # 4 documents of ~2^30 each
+    assert e.value.status == wc.WC_EOVERFLOW
 
 
 def test_merge_long_words_and_collisions():
@@ -609,6 +827,65 @@ def test_server_large_upload_and_packed_large_documents():
     srv.close()
 
 
+def test_server_serving_workload_requests():
+    """Requests cut from the serving workload's text (500,000-word vocabulary, Zipf 1.05,
+    lognormal sizes), among them one of 10 MiB and one just under the 64 MiB cap: each result is
+    the oracle's table, and the large ones are the same alone and in the mix."""
+    w = synth.WORKLOADS["serving"]
+    vocab, vlens = synth.make_vocab(w.vocab, w.max_len, w.seed)
+    sizes = [int(x) for x in np.minimum(
+        synth.lognormal_sizes(48, *w.lognormal, seed=w.seed + 7919 + 5), 4 << 20)]
+    big = {7: (10 << 20) + 333, 23: (64 << 20) - 1000}
+    for i, n in big.items():
+        sizes[i] = n
+    total = sum(sizes)
+    say("serving requests", len(sizes), "bytes", total)
+    c = synth.gen_stream(total, vocab, vlens, synth.zipf_probs(w.vocab, w.zipf_s), w.seed + 11,
+                         DEV)
+    host = c.text.cpu().numpy()
+    del c
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    texts = [host[a:a + n] for a, n in zip(starts, sizes)]
+    want = {i: oracle.count(t).as_dict() for i, t in enumerate(texts)}
+    alone = wc.Server(mem_budget=1 << 30, max_streams=1)
+    a = {i: wc.result_to_dict(alone.wait(alone.submit(texts[i]))) for i in big}
+    alone.close()
+    mix = wc.Server(mem_budget=768 << 20, max_streams=4)
+    ids = [mix.submit(t) for t in texts]
+    for i, rid in enumerate(ids):
+        got = wc.result_to_dict(mix.wait(rid))
+        assert got == want[i], i
+        if i in big:
+            assert a[i] == got, i
+    m = mix.merge([ids[i] for i in big])
+    assert wc.result_to_dict(mix.wait(m)) == \
+        oracle.count(b"".join(texts[i].tobytes() for i in big),
+                     np.cumsum([0] + [sizes[i] for i in big])).as_dict()
+    mix.close()
+
+
+def test_server_release_during_merge():
+    """Inputs released right after a merge is submitted stay readable until the merge has
+    read them (their memory is freed afterwards), while new requests reuse the pool."""
+    texts = _requests(24, 5)
+    srv = wc.Server(mem_budget=32 << 20, max_streams=3)
+    ids = [srv.submit(t) for t in texts[:8]]
+    for i in ids:
+        srv.wait(i)
+    m = srv.merge(ids)
+    for i in ids:
+        srv.release(i)        # before the merge has necessarily run
+    more = [srv.submit(t) for t in texts[8:]]   # reuse of the released memory
+    want = oracle.count(b"".join(texts[:8]), np.cumsum([0] + [len(t) for t in texts[:8]]))
+    assert wc.result_to_dict(srv.wait(m)) == want.as_dict()
+    for t, i in zip(texts[8:], more):
+        assert wc.result_to_dict(srv.wait(i)) == oracle.count(t).as_dict()
+    with pytest.raises(wc.WcError) as e:
+        srv.merge([ids[0]])   # released: no longer a request of the server
+    assert e.value.status == wc.WC_EINVAL
+    srv.close()
+
+
 def test_server_budget_errors():
     srv = wc.Server(mem_budget=4 << 20, max_streams=1)
     with pytest.raises(wc.WcError) as e:
@@ -653,3 +930,100 @@ def test_per_doc_chunk_sizes(chunk):
     c = synth.generate("batched-100k", scale=0.002)
     check(c.text.numpy(), c.offsets.numpy(), per_doc=True,
           tuning=wc.make_tuning(chunk_bytes=chunk, lds_load_pct=50))
+
+
+# ------------------------------------------------------------------------------------------
+# UTF-8 tokeniser (Section 5.2's other languages)
+# ------------------------------------------------------------------------------------------
+
+UTF8_ALPHABET = [b"a", b"Z", b" ", b"\xc3", b"\xa9", b"\xe2", b"\x80", b"\x94", b"\xf0",
+                 b"\x9f", b"\xed", b"\xa0"]
+
+
+def check_utf8(text, offsets=None, per_doc=False, **kw):
+    want = oracle.count(text, offsets, per_doc=per_doc, utf8=True)
+    got = gpu_count(text, offsets, per_doc=per_doc, utf8=True, **kw)
+    assert got.total_tokens == want.total
+    g, w = got.as_dict(), want.as_dict()
+    if g != w:
+        missing = [k for k in w if k not in g][:5]
+        extra = [k for k in g if k not in w][:5]
+        wrong = [(k, g[k], w[k]) for k in w if k in g and g[k] != w[k]][:5]
+        raise AssertionError(f"mismatch: missing {missing} extra {extra} wrong {wrong}")
+    return got
+
+
+def test_utf8_every_short_string_as_a_document():
+    docs = [b"".join(p) for n in range(0, 5) for p in itertools.product(UTF8_ALPHABET, repeat=n)]
+    text, off = join_docs(docs)
+    say("docs", len(docs), "bytes", len(text))
+    check_utf8(text, off)
+    check_utf8(text, off, per_doc=True)
+
+
+@pytest.mark.parametrize("stage", [4096, 8192])
+def test_utf8_random_bytes_stage_edges_and_cuts(stage):
+    """Mostly multi-byte text, sequences cut by stage edges (every shift of the corpus) and by
+    document boundaries, words longer than 16 bytes, and 16-byte words with a byte >= 0x80 at
+    positions 7 or 15 (stored as long words)."""
+    rng = np.random.default_rng(stage)
+    pieces = np.frombuffer(b"ab \xc3\xa9\xe2\x80\x94\xe6\x97\xa5\xf0\x9f\x98\x80\xce\xa9.", np.uint8)
+    raw = rng.choice(pieces, 3 * stage).tobytes()
+    special = ("aaaaaaaé" + "bbbbbbé" + " " + "ccccccccccccccé" + " " + "日本語のテキスト、"
+               + "ddddddddddddddddddddddé ").encode()
+    text = raw + special * 50 + raw[::-1]
+    tu = wc.make_tuning(stage_bytes=stage)
+    for shift in (0, 1, 3, 15):
+        t = b"q" * shift + text
+        say("stage", stage, "shift", shift)
+        check_utf8(t, tuning=tu)
+        off = synth.random_splits(len(t), 40 + shift, shift)
+        check_utf8(t, off, tuning=tu)
+        check_utf8(t, off, per_doc=True, tuning=tu)
+
+
+def test_utf8_multilingual_and_ascii_agreement():
+    text = ("Grüße aus Köln — naïve CAFÉ; Ωμέγα και άλφα… 日本語のテキスト、テスト。"
+            "Привет, мир! ‘quoted’ “double” 5×3÷2 Zebra zebra\ufeffword ").encode() * 3000
+    got = check_utf8(text)
+    assert got.as_dict()["grüße".encode()] == 3000
+    c = synth.generate("plain-1MB")
+    a = gpu_count(c.text.numpy(), c.offsets.numpy(), utf8=True)
+    assert a.as_dict() == c.expected_table()
+    check_utf8(c.text.numpy(), c.offsets.numpy(), per_doc=True)
+    # merging tables of UTF-8 words (16-byte words with high bytes take the long form)
+    t1 = check_utf8(text[:len(text) // 2])
+    t2 = check_utf8(text[len(text) // 2:])
+    assert wc.merge([t1, t2]).as_dict() == oracle.count(
+        text, [0, len(text) // 2, len(text)], utf8=True).as_dict()
+
+
+# ------------------------------------------------------------------------------------------
+# count from host memory, transfer pieces overlapped with counting
+# ------------------------------------------------------------------------------------------
+
+def test_count_host_pieces_match_oracle():
+    """Pieces of 1 MiB cut at delimiters: the table equals the oracle's for a stream of several
+    pieces, with documents of random sizes, a run of 3 MB without a delimiter across piece
+    boundaries, pinned and pageable host input, and the UTF-8 reading."""
+    c = synth.generate("stream-8GiB", scale=1 / 1024)          # 8 MiB, one document
+    base = c.text.numpy()
+    got = wc.count_host(base, piece_bytes=1 << 20)
+    assert got.as_dict() == c.expected_table() and got.total_tokens == c.n_tokens
+    pinned = torch.from_numpy(base.copy()).pin_memory()
+    assert wc.count_host(pinned, piece_bytes=1 << 20).as_dict() == c.expected_table()
+    text = np.concatenate([base[:2_500_000], np.frombuffer(b"x" * 3_000_000, np.uint8),
+                           base[2_500_000:5_000_000]])
+    off = synth.random_splits(len(text), 300, 9)
+    want = oracle.count(text, off).as_dict()
+    for piece in (1 << 20, 3 << 20):
+        g = wc.count_host(text, off, piece_bytes=piece)
+        assert g.as_dict() == want
+    # one table from pieces equals the plain count of the same text on the device
+    assert wc.count_host(text, off, piece_bytes=1 << 20, count_bytes=4).as_dict() == \
+        gpu_count(text, off, count_bytes=4).as_dict()
+    u = ("Grüße aus Köln — naïve CAFÉ; 日本語のテキスト、テスト。 ").encode() * 60_000
+    assert wc.count_host(u, piece_bytes=1 << 20, utf8=True).as_dict() == \
+        oracle.count(u, utf8=True).as_dict()
+    e = wc.count_host(b"", [0, 0])
+    assert e.n_entries == 0 and e.total_tokens == 0
