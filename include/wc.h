@@ -303,9 +303,14 @@ typedef struct wc_server wc_server;
 wc_status wc_server_create(int device, uint64_t mem_budget, uint32_t max_streams,
                            wc_server** out);
 
-/* Submit a count: text (host memory, copied at submission, or device memory that must stay
- * valid until the request completes when text_on_device != 0), host offsets[n_docs + 1].
- * opts->mode must be WC_GLOBAL. Returns the request id in *req_id. */
+/* Where the text of a submitted request is (wc_server_submit's text_on_device): */
+#define WC_TEXT_HOST_COPY     0  /* host memory, copied at submission (free it at once) */
+#define WC_TEXT_DEVICE        1  /* device memory, valid until the request completes */
+#define WC_TEXT_HOST_IN_PLACE 2  /* host memory read in place, valid until the request
+                                    completes; pinned memory is transferred without staging */
+
+/* Submit a count: text (see WC_TEXT_*), host offsets[n_docs + 1]. opts->mode must be
+ * WC_GLOBAL. Returns the request id in *req_id. */
 wc_status wc_server_submit(wc_server* s, const uint8_t* text, uint64_t len,
                            const uint64_t* offsets, uint64_t n_docs, int text_on_device,
                            const wc_opts* opts, uint64_t* req_id);

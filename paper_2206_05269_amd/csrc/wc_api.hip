@@ -245,7 +245,9 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
     // text over 500,000 words has one distinct word per 16 bytes at 32 KiB, per 22 at 256 KiB,
     // per 30 at 1 MiB), and a table that overflows costs a whole second count; long texts hit
     // the cap below
-    uint64_t want = per_doc ? len / 8 : len / 16;
+    // per document: a (document, word) pair per 8 bytes, and room for two per document (a
+    // corpus of tiny documents has about one pair per document)
+    uint64_t want = per_doc ? std::max<uint64_t>(len / 8, 2 * n_docs) : len / 16;
     want = std::max<uint64_t>(want, 4096);
     want = std::min<uint64_t>(want, per_doc ? (1ull << 28) : (1ull << 22));
     S = next_pow2(want);

@@ -49,6 +49,7 @@ struct Request {
   uint64_t id = 0;
   std::vector<uint8_t> text;      // host copy (host input)
   const uint8_t* dev_text = nullptr;
+  const uint8_t* host_text = nullptr;  // caller's host memory, read in place (not copied)
   uint64_t len = 0;
   std::vector<uint64_t> offsets;
   wc_opts opts{};
@@ -330,6 +331,8 @@ void run_group(wc_server* S, int idx, std::vector<std::shared_ptr<Request>>& G) 
     hipError_t e = hipSuccess;
     for (auto& r : G) {
       if (r->dev_text) e = hipMemcpyAsync(d_text + pos, r->dev_text, r->len, hipMemcpyDeviceToDevice, s);
+      else if (r->host_text && r->len)  // in place: pinned memory goes straight to the DMA engine
+        e = hipMemcpyAsync(d_text + pos, r->host_text, r->len, hipMemcpyHostToDevice, s);
       else if (r->len) e = upload(S->staging[idx], d_text + pos, r->text.data(), r->len, s);
       if (e != hipSuccess) break;
       if (packed) {
@@ -508,6 +511,9 @@ wc_status wc_server_submit(wc_server* S, const uint8_t* text, uint64_t len,
                            const uint64_t* offsets, uint64_t n_docs, int text_on_device,
                            const wc_opts* opts, uint64_t* req_id) {
   if (!S || !req_id || !opts || (len && !text) || !offsets) return WC_EINVAL;
+  if (text_on_device != WC_TEXT_HOST_COPY && text_on_device != WC_TEXT_DEVICE &&
+      text_on_device != WC_TEXT_HOST_IN_PLACE)
+    return WC_EINVAL;
   if (opts->count_bytes != 4 && opts->count_bytes != 8) return WC_EINVAL;
   if (opts->mode != WC_GLOBAL) return WC_EINVAL;  // per-request tables are global tables
   for (uint64_t i = 0; i < n_docs; ++i)
@@ -522,7 +528,8 @@ wc_status wc_server_submit(wc_server* S, const uint8_t* text, uint64_t len,
   if (p.workspace_bytes + len + (n_docs + 1) * 8 + 1024 > S->budget) return WC_ENOMEM;
   auto R = std::make_shared<Request>();
   R->len = len;
-  if (text_on_device) R->dev_text = text;
+  if (text_on_device == WC_TEXT_DEVICE) R->dev_text = text;
+  else if (text_on_device == WC_TEXT_HOST_IN_PLACE) R->host_text = text;
   else R->text.assign(text, text + len);
   R->offsets.assign(offsets, offsets + n_docs + 1);
   R->opts = o;

@@ -311,7 +311,7 @@ def count(corpus: torch.Tensor, offsets: Optional[torch.Tensor] = None, *, count
                             ctypes.c_void_p(offsets.data_ptr()), n_docs, ctypes.byref(o),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(res),
                             _stream_handle(stream))
-        if st == WC_ETABLEFULL and regrow and not per_doc:
+        if st == WC_ETABLEFULL and regrow:
             table_slots = 2 * int(p.table_slots)
             continue
         if st == WC_ENOMEM and regrow and per_doc:
@@ -634,29 +634,37 @@ class Server:
         if st != WC_OK:
             raise WcError(st, "wc_server_create")
         self._h = h
+        self._keep = {}  # texts the server reads in place, until their request is released
 
-    def submit(self, text, offsets=None, *, count_bytes: int = 8) -> int:
-        """text: bytes / uint8 numpy array (host, copied) or a CUDA uint8 tensor (must stay
-        alive until the request completes)."""
-        on_dev = isinstance(text, torch.Tensor) and text.is_cuda
-        if on_dev:
-            n = text.numel()
-            ptr = ctypes.c_void_p(text.data_ptr())
-            keep = None
+    def submit(self, text, offsets=None, *, count_bytes: int = 8, in_place: bool = False) -> int:
+        """text: bytes / uint8 numpy array / CPU uint8 tensor (host: copied at submission, or
+        with in_place=True read in place and kept alive here until released; a pinned tensor
+        then goes to the device without staging), or a CUDA uint8 tensor (kept alive likewise)."""
+        if isinstance(text, torch.Tensor) and text.is_cuda:
+            n, ptr, keep, where = text.numel(), text.data_ptr(), text, 1
+        elif isinstance(text, torch.Tensor):
+            if text.dtype != torch.uint8 or not text.is_contiguous():
+                raise ValueError("text must be a contiguous uint8 tensor")
+            n, keep = text.numel(), text
+            ptr = text.data_ptr() if n else np.zeros(1, np.uint8).ctypes.data
+            where = 2 if in_place else 0
         else:
             buf = np.frombuffer(bytes(text), dtype=np.uint8) if isinstance(text, (bytes, bytearray)) \
                 else np.ascontiguousarray(text, dtype=np.uint8)
             n = len(buf)
             keep = buf if n else np.zeros(1, np.uint8)
-            ptr = keep.ctypes.data_as(ctypes.c_void_p)
+            ptr = keep.ctypes.data
+            where = 2 if in_place else 0
         off = np.ascontiguousarray([0, n] if offsets is None else offsets, dtype=np.uint64)
         o = _opts(count_bytes, False, 0, None, 0, 0, 0)
         rid = ctypes.c_uint64()
-        st = lib().wc_server_submit(self._h, ptr, n, off.ctypes.data_as(ctypes.c_void_p),
-                                    len(off) - 1, 1 if on_dev else 0, ctypes.byref(o),
-                                    ctypes.byref(rid))
+        st = lib().wc_server_submit(self._h, ctypes.c_void_p(ptr), n,
+                                    off.ctypes.data_as(ctypes.c_void_p), len(off) - 1, where,
+                                    ctypes.byref(o), ctypes.byref(rid))
         if st != WC_OK:
             raise WcError(st, "wc_server_submit")
+        if where:
+            self._keep[int(rid.value)] = keep
         return int(rid.value)
 
     def poll(self, rid: int):
@@ -687,6 +695,7 @@ class Server:
 
     def release(self, rid: int):
         lib().wc_server_release(self._h, rid)
+        self._keep.pop(int(rid), None)
 
     def launches(self) -> int:
         return int(lib().wc_server_launches(self._h))
@@ -695,6 +704,7 @@ class Server:
         if getattr(self, "_h", None):
             lib().wc_server_destroy(self._h)
             self._h = None
+            self._keep = {}
 
     def __del__(self):
         try:

@@ -896,6 +896,23 @@ def test_server_budget_errors():
     srv.close()
 
 
+def test_server_host_in_place_input():
+    """Host text read in place (not copied at submission): pageable and pinned tensors and a
+    numpy array, each request's table equals the oracle's."""
+    texts = _requests(12, 8)
+    srv = wc.Server(mem_budget=128 << 20, max_streams=3)
+    ids = []
+    for i, t in enumerate(texts):
+        a = np.frombuffer(t, np.uint8)
+        x = a if i % 3 == 0 else (torch.from_numpy(a.copy()) if i % 3 == 1
+                                  else torch.from_numpy(a.copy()).pin_memory())
+        ids.append(srv.submit(x, in_place=True))
+    for t, i in zip(texts, ids):
+        assert wc.result_to_dict(srv.wait(i)) == oracle.count(t).as_dict()
+        srv.release(i)
+    srv.close()
+
+
 def test_server_device_input():
     c = synth.generate("plain-1MB")
     t = c.text.to(DEV)
