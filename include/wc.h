@@ -196,6 +196,27 @@ wc_status wc_count_host(const uint8_t* h_corpus, uint64_t corpus_len, const uint
                         uint8_t* d_text, void* d_workspace, uint64_t workspace_bytes,
                         wc_result* out, void* stream);
 
+/* wc_count for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same count into one global
+ * table (opts->mode must be WC_GLOBAL; the one-pass kernel always runs), with the hash table,
+ * header and other scratch in a static device array of the library (34 MiB per GPU, loaded
+ * with the library and held until the process ends) instead of a caller workspace. The
+ * caller passes the outputs: d_word_offsets uint64[max_entries + 1], d_counts
+ * (count_bytes each) [max_entries] and d_words uint8[word_bytes_cap]; *out points into them.
+ * Limits: table_slots at most 2^20 (0 = sized from the input as wc_count_plan, capped at
+ * 2^20), max_entries >= the table slots used, and a corpus whose per-stage cursor still fits
+ * the array (about 1 GiB); beyond them the call returns WC_ENOMEM before any device work.
+ * Makes no hipMalloc/hipFree and calls no allocating library routine. Every call on a GPU
+ * uses that GPU's one array, so calls that overlap on one GPU (two host threads, or two
+ * streams in flight) race and must be serialised by the caller; each call clears what must
+ * start at zero. Errors otherwise as wc_count (WC_ETABLEFULL: rerun with more slots, up to the
+ * limit; WC_ENOMEM also when the words exceed word_bytes_cap, out->word_bytes then holding
+ * the bytes needed). */
+wc_status wc_count_static(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t* d_offsets,
+                          uint64_t n_docs, const wc_opts* opts, uint64_t* d_word_offsets,
+                          void* d_counts, uint64_t max_entries, uint8_t* d_words,
+                          uint64_t word_bytes_cap, wc_result* out, void* stream);
+
 /* Plan a wc_merge of k tables (Section 3.3: the grouped counts of each word are summed).
  * Uses the inputs' host-side sizes only. */
 wc_status wc_merge_plan(const wc_result* const* tables, uint32_t k, const wc_opts* opts,

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "wc_internal.h"
@@ -1540,6 +1541,80 @@ wc_status wc_count_host(const uint8_t* h_corpus, uint64_t corpus_len, const uint
   }
   if (st == WC_OK) out->n_docs = n_docs;
   return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// allocation-free count: wc_count's one-pass global table in a static device array
+// ------------------------------------------------------------------------------------------
+namespace {
+
+constexpr uint64_t kStaticScratchBytes = 34ull << 20;
+constexpr uint64_t kStaticMaxSlots = 1ull << 20;  // 32 MiB of table
+constexpr int kMaxDevices = 64;
+
+// Header, table, per-stage document cursor and export block sums of wc_count_static. One copy
+// per GPU, loaded with the library and held until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress gives on each device.
+__device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t scratch_addr(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+wc_status wc_count_static(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t* d_offsets,
+                          uint64_t n_docs, const wc_opts* opts, uint64_t* d_word_offsets,
+                          void* d_counts, uint64_t max_entries, uint8_t* d_words,
+                          uint64_t word_bytes_cap, wc_result* out, void* stream) {
+  if (!opts_ok(opts) || !out || !d_offsets || !d_word_offsets || !d_counts || !d_words)
+    return WC_EINVAL;
+  if (corpus_len && !d_corpus) return WC_EINVAL;
+  if (opts->mode != WC_GLOBAL || (opts->debug_flags & WC_DEBUG_SPILL)) return WC_EINVAL;
+  if (opts->table_slots > kStaticMaxSlots) return WC_ENOMEM;
+  wc_opts o = *opts;
+  o.debug_flags = (o.debug_flags | WC_DEBUG_DIRECT) & ~WC_DEBUG_TIME;  // one-pass, no events
+  if (!o.table_slots) {
+    wc_plan p;
+    wc_status st = wc_count_plan(corpus_len, n_docs, &o, &p);
+    if (st != WC_OK) return st;
+    o.table_slots = std::min<uint64_t>(p.table_slots, kStaticMaxSlots);
+  }
+  Tune tu;
+  if (!resolve_tuning(o.tuning, &tu)) return WC_EINVAL;
+  global_stage(corpus_len, &o, &tu);
+  if (max_entries < o.table_slots) return WC_ENOMEM;
+  OutBufs ob{d_word_offsets, d_counts, d_words, word_bytes_cap};
+  CountLayout L;
+  if (!layout_count(corpus_len, n_docs, &o, tu, d_corpus, nullptr, &L, &ob)) return WC_EDEVICE;
+  if (L.total > kStaticScratchBytes) return WC_ENOMEM;  // the stage cursor of a huge corpus
+  void* base = nullptr;
+  HIPCHK(scratch_addr(&base));
+  if (!layout_count(corpus_len, n_docs, &o, tu, d_corpus, base, &L, &ob)) return WC_EDEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(ensure_smem_attr());
+  // count_table clears the header and the table (fill kernels) before counting
+  return count_table(d_corpus, corpus_len, d_offsets, n_docs, &o, tu, L, out, s);
 }
 
 }  // extern "C"

@@ -93,6 +93,8 @@ def lib():
         L.wc_count_plan.argtypes = [u64, u64, ctypes.POINTER(Opts), ctypes.POINTER(Plan)]
         L.wc_count.argtypes = [vp, u64, vp, u64, ctypes.POINTER(Opts), vp, u64,
                                ctypes.POINTER(Result), vp]
+        L.wc_count_static.argtypes = [vp, u64, vp, u64, ctypes.POINTER(Opts), vp, vp, u64, vp,
+                                      u64, ctypes.POINTER(Result), vp]
         L.wc_count_host_plan.argtypes = [u64, u64, ctypes.POINTER(Opts), u64, ctypes.POINTER(Plan)]
         L.wc_count_host.argtypes = [vp, u64, vp, u64, ctypes.POINTER(Opts), u64, vp, vp, u64,
                                     ctypes.POINTER(Result), vp]
@@ -146,7 +148,7 @@ def lib():
         L.wc_batch_destroy.argtypes = [vp]
         for f in ("wc_batch_plan", "wc_batch_create", "wc_batch_run", "wc_batch_destroy"):
             getattr(L, f).restype = ctypes.c_int32
-        for f in ("wc_count_plan", "wc_count", "wc_count_host_plan",
+        for f in ("wc_count_plan", "wc_count", "wc_count_static", "wc_count_host_plan",
                   "wc_count_host", "wc_merge_dense_plan",
                   "wc_merge_dense", "wc_merge_plan", "wc_merge", "wc_topk_ratio_plan",
                   "wc_topk_ratio", "wc_hash_words"):
@@ -332,6 +334,53 @@ def count(corpus: torch.Tensor, offsets: Optional[torch.Tensor] = None, *, count
         if st != WC_OK:
             raise WcError(st, "wc_count")
         return Table(res, ws)
+
+
+def count_static(corpus: torch.Tensor, offsets: Optional[torch.Tensor] = None, *,
+                 count_bytes: int = 8, table_slots: int = 0, tuning: Optional[Tuning] = None,
+                 debug_flags: int = 0, debug_hash_bits: int = 0, word_bytes_cap: int = 0,
+                 stream=None, regrow: bool = True) -> Table:
+    """wc_count_static: count into one global table whose scratch is the library's static
+    device array; only the output arrays are allocated here (one tensor). With regrow, a full
+    table is counted again with twice the slots (up to the static limit of 2^20) and an
+    exported-word overflow with the reported byte count; other errors raise WcError."""
+    _require_cuda(corpus, "corpus")
+    if corpus.dtype != torch.uint8 or corpus.dim() != 1 or not corpus.is_contiguous():
+        raise ValueError("corpus must be a contiguous 1-D uint8 tensor")
+    n = corpus.numel()
+    if offsets is None:
+        offsets = torch.tensor([0, n], dtype=torch.int64, device=corpus.device)
+    _require_cuda(offsets, "offsets")
+    n_docs = offsets.numel() - 1
+    limit = 1 << 20  # the largest table the library's static scratch holds
+    while True:
+        o = _opts(count_bytes, False, table_slots, tuning, debug_flags, debug_hash_bits,
+                  word_bytes_cap)
+        p = Plan()
+        st = lib().wc_count_plan(n, n_docs, ctypes.byref(o), ctypes.byref(p))
+        if st != WC_OK:
+            raise WcError(st, "wc_count_plan")
+        max_e = min(int(p.table_slots), limit) if not table_slots else int(table_slots)
+        wcap = int(p.word_bytes_cap)
+        a = (8 * (max_e + 1) + 255) // 256 * 256
+        b = (count_bytes * max_e + 255) // 256 * 256
+        buf = _alloc(a + b + wcap, corpus.device)
+        base = buf.data_ptr()
+        res = Result()
+        st = lib().wc_count_static(ctypes.c_void_p(corpus.data_ptr()), n,
+                                   ctypes.c_void_p(offsets.data_ptr()), n_docs, ctypes.byref(o),
+                                   ctypes.c_void_p(base), ctypes.c_void_p(base + a), max_e,
+                                   ctypes.c_void_p(base + a + b), wcap, ctypes.byref(res),
+                                   _stream_handle(stream))
+        if st == WC_ETABLEFULL and regrow and max_e < limit:
+            table_slots = min(2 * max_e, limit)
+            continue
+        if st == WC_ENOMEM and regrow and res.word_bytes > wcap:
+            word_bytes_cap = int(res.word_bytes)
+            continue
+        if st != WC_OK:
+            raise WcError(st, "wc_count_static")
+        return Table(res, buf)
 
 
 def count_host(text, offsets=None, *, piece_bytes: int = 256 << 20, count_bytes: int = 8,
