@@ -140,10 +140,10 @@ typedef struct wc_result {
   float total_ms;            /* WC_DEBUG_TIME: duration of the whole call on the device */
   /* Per-call statistics of the two-pass global count (zero for the other paths):
    * [0] tokens written as records to the hash partitions (words missing the dictionary),
-   * [1] records pass 1 added straight to the global table because their partition's
-   *     arena region was used up,
+   * [1] records pass 1 added straight to the global table because the workgroup's share of
+   *     their partition's arena blocks was used up,
    * [2] dictionary words,
-   * [3] rounds a pass-1 wave waited for a partition ring slot or for a chunk to leave,
+   * [3] 0 (reserved),
    * [4] records pass 2 could not sum in its LDS table (added to the global table). */
   uint64_t stats[5];
 } wc_result;

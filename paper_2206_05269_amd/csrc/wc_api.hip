@@ -307,14 +307,14 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
     L->dict_cap = std::min<uint32_t>(o->tuning && o->tuning->lds_entries ? tu.lds : kDictMax,
                                      kDictMax);
     // Each workgroup owns J interleaved blocks of every partition: room for one record per
-    // 16 bytes of text spread evenly; a quarter more is handed out on demand to workgroups
-    // that need it. A partition that still runs out counts in the global table.
+    // 12.8 bytes of text spread evenly (Zipf text spills about one per 23 bytes); a partition
+    // of a workgroup that runs out counts the rest in the global table.
     const uint64_t blk_bytes = (uint64_t)kBlockRec * 16;
     const uint64_t per = grid * kParts * kBlockRec;  // records per static round of blocks
-    const uint64_t J = std::max<uint64_t>(1, (len / 16 + per - 1) / per);
+    const uint64_t J = std::max<uint64_t>(1, (len * 5 / 64 + per - 1) / per);
     const uint64_t S = J * grid;
     L->static_blocks = (uint32_t)S;
-    const uint64_t R = S + std::max<uint64_t>(64, S / 4);
+    const uint64_t R = S;
     if ((uint64_t)kParts * R >= (1ull << 32)) return false;  // block indices are 32-bit
     L->R = (uint32_t)R;
     L->arena = B.take<uint4>((uint64_t)kParts * L->R * blk_bytes);

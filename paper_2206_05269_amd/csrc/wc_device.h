@@ -60,9 +60,9 @@ struct Header {
   uint64_t work_next;     // work-queue cursor (persistent launches)
   uint64_t out_cursor;    // per-document output: (entries << 32) | word bytes reserved
   uint64_t arena_next;    // per-document output: private-table slots taken
-  // two-pass global count statistics: records written to the partitions, tokens pass 1
-  // counted straight in the global table, dictionary words, records staged again after
-  // their partition's LDS staging was full, records pass 2 could not sum in LDS
+  // two-pass global count statistics: records written to the partitions, records pass 1
+  // counted straight in the global table, dictionary words, (unused), records pass 2 could
+  // not sum in LDS
   uint64_t stat[5];
   uint64_t pad[2];
 };

@@ -45,7 +45,9 @@ WC_DEV uint32_t part_of(uint32_t h) { return h & (kParts - 1); }
 // field of h (bits 9-16, or bits 17-24 when bit 8 of the group's displacement is set) XOR the
 // displacement's low 8 bits.
 WC_DEV uint32_t dict_group(uint32_t h) { return h & (kDispBuckets - 1); }
-WC_DEV uint32_t dict_field(uint32_t h, uint32_t sel) { return (h >> (9 + 8 * sel)) & 0xffu; }
+WC_DEV uint32_t dict_field(uint32_t h, uint32_t sel) {
+  return (h >> (__builtin_ctz(kDispBuckets) + 8 * sel)) & 0xffu;
+}
 WC_DEV uint32_t dict_slot(uint32_t h, uint32_t d) {
   const uint32_t g = dict_group(h);
   return ((g & (kDictRegions - 1)) << 8) | ((dict_field(h, (d >> 8) & 1u) ^ d) & 0xffu);
@@ -528,8 +530,9 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
     }
   }
   __syncthreads();
-  const uint32_t lane = tid & 63, r = tid >> 6;  // wave r fills region r
-  if (r < kDictRegions) {
+  const uint32_t lane = tid & 63;
+  // wave v fills regions v, v + 16, ...
+  for (uint32_t r = tid >> 6; r < kDictRegions; r += blockDim.x / 64) {
     // the region's groups g = r + 16 L, largest first
     const uint32_t my_n = lane < kRegionGroups ? s_gn[r + kDictRegions * lane] : 0u;
     uint32_t rank = 0;
@@ -622,10 +625,9 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
 constexpr int kMapWaves = kMapBlock / 64;
 constexpr uint32_t kLongEnd = 0x7ffu;                    // word end not within the staged bytes
 constexpr uint32_t kBndWords = kStripeText / 32 + 1;     // document-start bits of a stripe
-constexpr uint32_t kSpinLimit = 1u << 24;                // rounds of one wait before giving up
 
 size_t global_map_dyn(uint32_t dict_cap) {
-  return (size_t)kParts * kStageSlots * 16 + (size_t)kMapWaves * kStripeText +
+  return (size_t)kMapWaves * kStripeText +
          (size_t)(kDispBuckets + kDictSlots) * 2 + (size_t)(dict_cap + 1) * 16 + (size_t)dict_cap * 4 +
          (size_t)kMapWaves * kWaveStarts * 4;
 }
@@ -663,46 +665,35 @@ WC_DEV void write_pairs(uint32_t m, uint32_t last16, uint32_t nl, uint32_t rank,
 }
 
 // One workgroup of BLOCK threads scans a contiguous range of STAGE-byte stages; wave v takes
-// the v-th 1 KiB stripe of every stage and runs on its own, with no workgroup barrier until
-// the range ends. Per stripe: classify 16 bytes per lane (plus the 16 bytes after the stripe,
-// for the word that crosses its end, and the byte before it), word start / end masks, a
-// wave-wide compaction of the (start, end) pairs, and one token per lane per round: counted in
-// the dictionary, or staged as a record in its partition's ring, or (longer than 16 bytes)
-// counted in the global table.
+// a contiguous run of the range's 1 KiB stripes and runs on its own, with no workgroup barrier
+// until the range ends. Per stripe: classify 16 bytes per lane (plus the byte before the
+// stripe), word start / end masks, a wave-wide compaction of the (start, end) pairs, and up to
+// two tokens per lane per round: counted in the dictionary, or written as a record to its
+// partition, or (longer than 16 bytes) counted in the global table.
 //
-// Partition rings. s_fill[p] = (head << 16) | count: records carry 16-bit tickets; head is the
-// ticket of the oldest record held, count the records reserved since. A token reserves ticket
-// head + count with one LDS atomic; with count < kStageSlots its slot (ticket mod kStageSlots)
-// is free and it writes the record at once, otherwise it waits until head has come within
-// kStageSlots of its ticket. The lane holding the last ticket of a chunk of 8 owns the chunk;
-// after each round of tokens a wave sends out the chunks its lanes own, 8 lanes per chunk (one
-// aligned 128-byte write). A chunk leaves when head has reached it and its 8 records are
-// written (a record's first dword is never 0); its slots are zeroed, then head moves on by 8.
-// Chunks of a partition so leave in ticket order, and the oldest chunk can always leave: its
-// records never wait for a slot, and a wave never waits without serving the chunks it owns.
+// Records. Each partition's records of this workgroup go to the workgroup's own blocks of the
+// partition's arena region, in the order of a per-partition ticket taken with one LDS atomic:
+// ticket t is slot t mod 256 of the workgroup's (t / 256)-th block, block j * G + w of the
+// region (G workgroups, this one w). Lanes store their records straight to the arena, one
+// 16-byte store each; the lines of a block fill in L2 before they are written back. The lane
+// holding a block's last slot sets its fill to full; the workgroup sets the fill of each
+// partition's last, partial block when its range is done. A partition whose share of blocks
+// is used up sends the rest of its records to the global table.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   constexpr int NW = BLOCK / 64;
   constexpr int STAGE = BLOCK * 16;
-  constexpr uint32_t kNone = 0xffffffffu;
-  constexpr uint32_t kRingMask = kStageSlots - 1;
   static_assert(STAGE == (int)kGlobalStage && NW * (int)kStripe == STAGE,
                 "a stage is one stripe per wave");
   static_assert(NW == kMapWaves && BLOCK >= (int)kParts, "one thread per partition at the end");
-  static_assert((kStageSlots & kRingMask) == 0 && kStageSlots >= 2 * kChunkRec &&
-                    65536 % kBlockRec == 0 && kWaveStarts == 128,
-                "16-bit tickets wrap at a multiple of the ring and the block; a round takes two "
-                "tokens per lane");
+  static_assert(kWaveStarts == 128, "a round takes two tokens per lane");
   extern __shared__ __align__(16) uint8_t s_dyn[];
-  __shared__ uint32_t s_fill[kParts];
-  __shared__ uint32_t s_blk[kParts];  // arena block p * R + b being filled, or kNone
+  __shared__ uint32_t s_tick[kParts];  // records of each partition so far
   __shared__ uint32_t s_bnd[NW][kBndWords];
-  __shared__ uint32_t s_dq[NW][8];
   __shared__ uint32_t s_stat[4];
 
   const uint32_t D = P.dict_cap;
-  uint4* s_stage = (uint4*)s_dyn;                               // [kParts][kStageSlots]
-  uint8_t* s_txt = (uint8_t*)(s_stage + kParts * kStageSlots);  // [NW][kStripeText]
+  uint8_t* s_txt = s_dyn;                                       // [NW][kStripeText]
   uint16_t* s_disp = (uint16_t*)(s_txt + NW * kStripeText);    // [kDispBuckets]
   uint16_t* s_dslot = s_disp + kDispBuckets;                    // [kDictSlots]
   uint4* s_keys = (uint4*)(s_dslot + kDictSlots);               // [D + 1]
@@ -723,30 +714,19 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   for (uint32_t i = tid; i < kDictSlots; i += BLOCK) s_dslot[i] = P.dict->slot[i];
   for (uint32_t i = tid; i <= nd; i += BLOCK) s_keys[i] = P.dict->keys[i];
   for (uint32_t i = tid; i < nd; i += BLOCK) s_cnt[i] = 0;
-  for (uint32_t i = tid; i < kParts * kStageSlots; i += BLOCK) s_stage[i] = make_uint4(0, 0, 0, 0);
-  // This workgroup's j-th own block of a partition is j * G + w; past its S / G own blocks it
-  // takes blocks from [S, R) with an atomic. A block is filled completely before the next, so
-  // the position in the current block is head mod kBlockRec.
-  const uint32_t G = gridDim.x, w = blockIdx.x;
-  for (uint32_t p = tid; p < kParts; p += BLOCK) {
-    s_fill[p] = 0;
-    s_blk[p] = w < P.S ? p * P.R + w : kNone;
-  }
+  for (uint32_t p = tid; p < kParts; p += BLOCK) s_tick[p] = 0;
   for (uint32_t i = tid; i < NW * kBndWords; i += BLOCK) (&s_bnd[0][0])[i] = 0;
   if (tid < 4) s_stat[tid] = 0;
   __syncthreads();
 
+  // This workgroup's j-th block of partition p is block j * G + w of region p (J = S / G
+  // blocks each).
+  const uint32_t G = gridDim.x, w = blockIdx.x;
+  const uint32_t J = P.S / G;
   uint8_t* const my_txt = s_txt + wv * kStripeText;
   uint32_t* const my_bnd = s_bnd[wv];
   uint32_t* const my_pairs = s_pairs + wv * kWaveStarts;
 
-  // the block after block gb (= p * R + b) of partition p, or kNone
-  auto next_block = [&](uint32_t p, uint32_t gb) -> uint32_t {
-    const uint32_t b = gb - p * P.R;
-    if (b + G < P.S) return gb + G;
-    const uint32_t d = P.S + atomicAdd(&P.cursor[p], 1u);
-    return d < P.R ? p * P.R + d : kNone;
-  };
   auto insert_record = [&](const uint4 r) {
     const uint64_t lo = (uint64_t)r.x | ((uint64_t)r.y << 32);
     const uint64_t hi = (uint64_t)r.z | ((uint64_t)r.w << 32);
@@ -764,68 +744,8 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     return P.offsets[a];
   };
 
-  uint32_t spilled = 0, direct = 0, waits = 0;
-  bool stalled = false;
+  uint32_t spilled = 0, direct = 0;
 
-  // One pass over up to 8 owned chunks, 8 lanes (one record each) per chunk; oval = (partition
-  // << 16) | last ticket. The owners are ranked (slot a first, then slot b) and the pass takes
-  // ranks rot, rot + 1, ... (mod the number of owners): successive passes of a wait turn the
-  // window, so every owned chunk gets its turn. Chunks that are not ready stay owned.
-  auto flush_pass = [&](bool& own_a, bool& own_b, uint32_t oval_a, uint32_t oval_b,
-                        uint32_t rot) {
-    const uint64_t oma = __ballot(own_a), omb = __ballot(own_b);
-    const uint32_t na = (uint32_t)__popcll(oma), no = na + (uint32_t)__popcll(omb);
-    if (rot) rot %= no;  // rot = 0 on a wait's first pass
-    uint32_t ia = __builtin_amdgcn_mbcnt_hi((uint32_t)(oma >> 32),
-                                            __builtin_amdgcn_mbcnt_lo((uint32_t)oma, 0u));
-    uint32_t ib = na + __builtin_amdgcn_mbcnt_hi((uint32_t)(omb >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)omb, 0u));
-    ia = ia >= rot ? ia - rot : ia + no - rot;
-    ib = ib >= rot ? ib - rot : ib + no - rot;
-    if (own_a && ia < 8) s_dq[wv][ia] = oval_a;
-    if (own_b && ib < 8) s_dq[wv][ib] = oval_b;
-    wave_sync();
-    const uint32_t nc = min(no, 8u);
-    const uint32_t g = lane >> 3, j = lane & 7;
-    bool ok = false;
-    uint32_t q = 0, start = 0, slot = 0, gb = 0;
-    uint4 r4 = make_uint4(0, 0, 0, 0);
-    if (g < nc) {
-      const uint32_t v = s_dq[wv][g];
-      q = v >> 16;
-      start = (v - (kChunkRec - 1)) & 0xffffu;
-      // head first: once it has reached the chunk, the slots hold the chunk's records or 0,
-      // and the partition's block is the one the chunk before left
-      const uint32_t head =
-          __hip_atomic_load(&s_fill[q], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >> 16;
-      slot = q * kStageSlots + ((start + j) & kRingMask);
-      r4 = s_stage[slot];
-      gb = s_blk[q];
-      ok = head == start && r4.x != 0;
-    }
-    const uint64_t okm = __ballot(ok);
-    if (g < nc && ((okm >> (8 * g)) & 0xffull) == 0xffull) {
-      const uint32_t bp = start & (kBlockRec - 1);
-      if (gb != kNone) {
-        P.arena[(uint64_t)gb * kBlockRec + bp + j] = r4;
-      } else {
-        ++direct;
-        insert_record(r4);
-      }
-      s_stage[slot] = make_uint4(0, 0, 0, 0);
-      if (j == 0) {
-        if (gb != kNone && bp + kChunkRec == kBlockRec) {
-          P.fill[gb] = (uint16_t)kBlockRec;
-          s_blk[q] = next_block(q, gb);
-        }
-        wave_sync();  // the zeroed slots before the ring moves on
-        atomicAdd(&s_fill[q], (kChunkRec << 16) - kChunkRec);  // head += 8 (mod 2^16)
-      }
-    }
-    if (own_a && ia < 8 && ((okm >> (8 * ia)) & 0xffull) == 0xffull) own_a = false;
-    if (own_b && ib < 8 && ((okm >> (8 * ib)) & 0xffull) == 0xffull) own_b = false;
-    wave_sync();  // s_dq is rewritten by the next pass
-  };
   // a word longer than 16 bytes (or with its end beyond the staged bytes): from device memory,
   // into the global table
   auto long_token = [&](int64_t p0, uint32_t s, uint32_t e) {
@@ -842,9 +762,23 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     }
   };
 
+  // A record of partition p: the next ticket of p places it in the workgroup's blocks; the
+  // lane that fills a block's last slot marks the block full.
+  auto place = [&](uint32_t p, const uint4 rec) {
+    const uint32_t t = atomicAdd(&s_tick[p], 1u);
+    const uint32_t j = t / kBlockRec, at = t % kBlockRec;
+    if (j < J) {
+      const uint64_t gb = (uint64_t)p * P.R + (uint64_t)j * G + w;
+      P.arena[gb * kBlockRec + at] = rec;
+      if (at == kBlockRec - 1) P.fill[gb] = (uint16_t)kBlockRec;
+    } else {
+      ++direct;  // the partition's share of blocks is used up
+      insert_record(rec);
+    }
+  };
+
   // One round: pairs t and t + 64 of this wave's list (t = lane), for those below nw. A token
-  // that misses the dictionary reserves a ticket and writes its record if the slot is free;
-  // then the wave places the records that waited and sends out the chunks its lanes own.
+  // that misses the dictionary becomes a record of its partition.
   auto token_round = [&](uint32_t nw, int64_t p0) {
     const uint32_t ta = lane, tb = lane + 64;
     const uint32_t pra = ta < nw ? my_pairs[ta] : 0u, prb = tb < nw ? my_pairs[tb] : 0u;
@@ -863,50 +797,9 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     if (ia >= 0) atomicAdd(&s_cnt[ia], 1u);
     if (ib >= 0) atomicAdd(&s_cnt[ib], 1u);
     const bool ma = fa && ia < 0, mb = fb && ib < 0;
-    const uint32_t pa = part_of(ha), pb = part_of(hb);
-    uint32_t oa = 0, ob = 0;
-    if (ma) oa = atomicAdd(&s_fill[pa], 1u);
-    if (mb) ob = atomicAdd(&s_fill[pb], 1u);
-    const uint32_t tka = ((oa >> 16) + oa) & 0xffffu, tkb = ((ob >> 16) + ob) & 0xffffu;
-    const uint4 reca = key4(loa, hia), recb = key4(lob, hib);
-    bool pend_a = ma && (oa & 0xffffu) >= kStageSlots, pend_b = mb && (ob & 0xffffu) >= kStageSlots;
-    if (ma && !pend_a) s_stage[pa * kStageSlots + (tka & kRingMask)] = reca;
-    if (mb && !pend_b) s_stage[pb * kStageSlots + (tkb & kRingMask)] = recb;
-    bool own_a = ma && (tka & (kChunkRec - 1)) == kChunkRec - 1;
-    bool own_b = mb && (tkb & (kChunkRec - 1)) == kChunkRec - 1;
+    if (ma) place(part_of(ha), key4(loa, hia));
+    if (mb) place(part_of(hb), key4(lob, hib));
     spilled += (ma ? 1u : 0u) + (mb ? 1u : 0u);
-    uint32_t spins = 0;
-    while (__any(pend_a || pend_b || own_a || own_b)) {
-      if (spins) __builtin_amdgcn_s_sleep(1);  // waiting on other waves
-      if (++spins >= kSpinLimit || stalled) {
-        stalled = true;
-        break;
-      }
-      if (pend_a) {
-        const uint32_t head =
-            __hip_atomic_load(&s_fill[pa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 16;
-        if (((tka - head) & 0xffffu) < kStageSlots) {
-          s_stage[pa * kStageSlots + (tka & kRingMask)] = reca;
-          pend_a = false;
-        }
-      }
-      if (pend_b) {
-        const uint32_t head =
-            __hip_atomic_load(&s_fill[pb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 16;
-        if (((tkb - head) & 0xffffu) < kStageSlots) {
-          s_stage[pb * kStageSlots + (tkb & kRingMask)] = recb;
-          pend_b = false;
-        }
-      }
-      // a chunk can leave only once the owner's own record is in it
-      bool fa2 = own_a && !pend_a, fb2 = own_b && !pend_b;
-      if (__any(fa2 || fb2)) {
-        flush_pass(fa2, fb2, (pa << 16) | tka, (pb << 16) | tkb, 8 * (spins - 1));
-        own_a = own_a && (pend_a || fa2);
-        own_b = own_b && (pend_b || fb2);
-      }
-    }
-    waits += spins > 1 ? spins - 1 : 0;
   };
 
   // Wave wv scans its own contiguous run of nsw stripes of the workgroup's range. The word
@@ -1044,47 +937,27 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     def = __builtin_amdgcn_readlane((int)ndef_j, 63) < 16;
     def_s = (uint32_t)__builtin_amdgcn_readlane((int)ndef_j, 63);
     carry = (uint32_t)__builtin_amdgcn_readlane((int)(w16 >> 15), 63);
-    if (stalled) break;
   }
   // a word running over the range's end: from device memory
-  if (def && !stalled) {
+  if (def) {
     tokens += 1;
     if (lane == 0) long_token(stripe_pos(nsw) - 16, def_s, kLongEnd);
   }
-  if (stalled) or32(&hdr->flags, kFlagStall);
 
-  // ---- end of range: the records still held leave, blocks close; dictionary hits go out ---
+  // ---- end of range: each partition's last block gets its fill; dictionary hits go out ----
   __syncthreads();
-  if (tid < (int)kParts && !(ld_relaxed32(&hdr->flags) & kFlagStall)) {
-    // fewer than kChunkRec records (every full chunk has left); the block has room for them
-    const uint32_t f = s_fill[tid], head = f >> 16;
-    uint32_t n = f & 0xffffu;
-    if (n >= kChunkRec) {  // a full chunk still held: never after a completed scan
-      or32(&hdr->flags, kFlagStall);
-      n = 0;
-    }
-    const uint32_t gb = s_blk[tid], bp = head & (kBlockRec - 1);
-    for (uint32_t j = 0; j < n; ++j) {
-      const uint4 r = s_stage[tid * kStageSlots + ((head + j) & kRingMask)];
-      if (gb != kNone) {
-        P.arena[(uint64_t)gb * kBlockRec + bp + j] = r;
-      } else {
-        ++direct;
-        insert_record(r);
-      }
-    }
-    if (gb != kNone) P.fill[gb] = (uint16_t)(bp + n);
+  if (tid < (int)kParts) {
+    const uint32_t t = s_tick[tid], j = t / kBlockRec, at = t % kBlockRec;
+    if (at && j < J) P.fill[(uint64_t)tid * P.R + (uint64_t)j * G + w] = (uint16_t)at;
   }
   for (uint32_t i = tid; i < nd; i += BLOCK) P.dict_part[(uint64_t)blockIdx.x * D + i] = s_cnt[i];
   if (spilled) atomicAdd(&s_stat[0], spilled);
   if (direct) atomicAdd(&s_stat[1], direct);
-  if (waits && lane == 0) atomicAdd(&s_stat[2], waits);
   if (lane == 0 && tokens) add64(&hdr->total_tokens, tokens);
   __syncthreads();
   if (tid == 0) {
     if (s_stat[0]) add64(&hdr->stat[0], s_stat[0]);
     if (s_stat[1]) add64(&hdr->stat[1], s_stat[1]);
-    if (s_stat[2]) add64(&hdr->stat[3], s_stat[2]);
   }
 }
 

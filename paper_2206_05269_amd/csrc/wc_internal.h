@@ -34,15 +34,13 @@ struct CountParams {
 
 // two-pass global count (wc_global.hip)
 constexpr uint32_t kParts = 256;         // partitions of the spilled records
-constexpr uint32_t kStageSlots = 16;     // records staged per partition in LDS (a ring)
-constexpr uint32_t kChunkRec = 8;        // records per write to the arena (128 bytes)
 constexpr uint32_t kBlockRec = 256;      // records per arena block (4 KiB)
-constexpr uint32_t kDictMax = 2560;      // hot-word dictionary capacity (words)
+constexpr uint32_t kDictMax = 5120;      // hot-word dictionary capacity (words)
 constexpr uint32_t kMapBlock = 1024;     // pass-1 workgroup
 constexpr uint32_t kGlobalStage = kMapBlock * 16;  // bytes scanned per pass-1 stage
-constexpr uint32_t kDispBuckets = 512;   // dictionary: displacement buckets (low 9 hash bits)
-constexpr uint32_t kDictSlots = 4096;    // dictionary: slots of the perfect hash
-constexpr uint32_t kDictRegions = 16;    // dictionary: regions of 256 slots (group mod 16)
+constexpr uint32_t kDispBuckets = 1024;   // dictionary: displacement buckets (low 9 hash bits)
+constexpr uint32_t kDictSlots = 8192;    // dictionary: slots of the perfect hash
+constexpr uint32_t kDictRegions = 32;    // dictionary: regions of 256 slots (group mod 16)
 constexpr uint32_t kSampleStages = 512;  // pass-1 stages sampled (first 8 KiB of each)
 constexpr uint32_t kSamplePer = 2;       // sampled stages per sample workgroup
 constexpr uint32_t kSampleLds = 2048;    // LDS table of one sample workgroup

@@ -202,7 +202,7 @@ class Table:
         """Per-call statistics of the two-pass global count (all zero on other paths)."""
         s = self.res.stats
         return {"spilled": int(s[0]), "arena_direct": int(s[1]), "dict_words": int(s[2]),
-                "ring_waits": int(s[3]), "reduce_overflow": int(s[4])}
+                "reduce_overflow": int(s[4])}
 
     def word_offsets(self) -> torch.Tensor:
         return self._view(self.res.d_word_offsets, 8 * (self.n_entries + 1), torch.int64)
