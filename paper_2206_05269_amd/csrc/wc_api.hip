@@ -118,10 +118,9 @@ struct CountLayout {
   uint64_t* sums;  // scan block totals
   // two-pass global count
   bool spill = false;
-  uint32_t spill_grid = 0, R = 0, static_blocks = 0, dict_cap = 0;
+  uint32_t spill_grid = 0, static_blocks = 0, dict_cap = 0;
   uint64_t spill_spw = 0;
   uint4* arena = nullptr;
-  uint32_t* cursor = nullptr;
   uint16_t* fill = nullptr;
   Slot* sample_table = nullptr;
   Header* sample_hdr = nullptr;
@@ -313,13 +312,10 @@ bool layout_count(uint64_t len, uint64_t n_docs, const wc_opts* o, const Tune& t
     const uint64_t per = grid * kParts * kBlockRec;  // records per static round of blocks
     const uint64_t J = std::max<uint64_t>(1, (len * 5 / 64 + per - 1) / per);
     const uint64_t S = J * grid;
+    if ((uint64_t)kParts * S >= (1ull << 32)) return false;  // block indices are 32-bit
     L->static_blocks = (uint32_t)S;
-    const uint64_t R = S;
-    if ((uint64_t)kParts * R >= (1ull << 32)) return false;  // block indices are 32-bit
-    L->R = (uint32_t)R;
-    L->arena = B.take<uint4>((uint64_t)kParts * L->R * blk_bytes);
-    L->cursor = B.take<uint32_t>(kParts * 4);
-    L->fill = B.take<uint16_t>((uint64_t)kParts * L->R * 2);
+    L->arena = B.take<uint4>((uint64_t)kParts * S * blk_bytes);
+    L->fill = B.take<uint16_t>((uint64_t)kParts * S * 2);
     L->sample_table = B.take<Slot>(kSampleSlots * sizeof(Slot));
     L->sample_hdr = B.take<Header>(sizeof(Header));
     L->dict = B.take<DictImage>(sizeof(DictImage));
@@ -564,17 +560,14 @@ wc_status count_table(const uint8_t* d_corpus, uint64_t corpus_len, const uint64
       G.dict_part = L.dict_part;
       G.sample_table = L.sample_table;
       G.sample_hdr = L.sample_hdr;
-      G.R = L.R;
       G.S = L.static_blocks;
       G.reduce_entries = kReduceLds;
       uint32_t pct = opts->tuning && opts->tuning->lds_load_pct ? opts->tuning->lds_load_pct : 100;
       pct = std::min<uint32_t>(std::max<uint32_t>(pct, 10), 100);
       G.reduce_cap = (uint32_t)((uint64_t)kReduceLds * pct / 100);
       G.arena = L.arena;
-      G.cursor = L.cursor;
       G.fill = L.fill;
-      HIPCHK(launch_fill_zero(L.cursor, kParts * 4, s));
-      HIPCHK(launch_fill_zero(L.fill, (uint64_t)kParts * L.R * 2, s));
+      HIPCHK(launch_fill_zero(L.fill, (uint64_t)kParts * L.static_blocks * 2, s));
       HIPCHK(launch_fill_zero(L.sample_table, kSampleSlots * sizeof(Slot), s));
       HIPCHK(launch_fill_zero(L.sample_hdr, sizeof(Header), s));
       HIPCHK(launch_fill_zero(L.dict, sizeof(DictImage), s));

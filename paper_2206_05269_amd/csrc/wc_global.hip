@@ -11,9 +11,8 @@
 //     key compare, with no insertion, eviction or probe loop.
 //   pass 1 (global_map_kernel): scan the text, each wave on its own 1 KiB stripes; a dictionary
 //     word is counted in LDS; any other token becomes a 16-byte record (its packed bytes) in one
-//     of 256 partitions chosen by a hash of the word. Records wait in an LDS ring per partition
-//     and leave in aligned 128-byte chunks into 4 KiB blocks of the partition's arena region,
-//     so the spill is sequential full-line writes.
+//     of 256 partitions chosen by a hash of the word, stored straight into the workgroup's
+//     current 4 KiB block of that partition (an LDS ticket per partition gives its slot).
 //   pass 2 (global_reduce_kernel): one workgroup per partition reads that partition's
 //     records, sums them in an LDS table and adds each distinct word once to the global
 //     table; it also totals the dictionary hits of its share of dictionary words.
@@ -645,40 +644,41 @@ WC_DEV uint32_t load_text4(const uint8_t* corpus, uint64_t len, int64_t p) {
   return w;
 }
 
-// (start, end) of each word starting in this lane's 16 bytes, in text order, for the ranks in
-// [w0, w0 + kWaveStarts): end from this lane's last-byte mask, else from the next lane's (nl),
-// else kLongEnd (the word runs past the next lane's bytes: longer than 16 bytes).
-WC_DEV void write_pairs(uint32_t m, uint32_t last16, uint32_t nl, uint32_t rank, uint32_t w0,
-                        uint32_t* pairs) {
-  const uint32_t pos0 = 16 + (threadIdx.x & 63) * 16;  // after the 16-byte prefix
+// Positions of the word starts in this lane's 16 bytes (after the 16-byte prefix), in text
+// order, for the ranks in [w0, w0 + kWaveStarts).
+WC_DEV void write_starts16(uint32_t m, uint32_t rank, uint32_t w0, uint16_t* starts) {
+  const uint32_t pos0 = 16 + (threadIdx.x & 63) * 16;
   while (m) {
     const uint32_t j = __ffs(m) - 1;
-    if (rank - w0 < kWaveStarts) {
-      const uint32_t bits = last16 >> j;
-      const uint32_t e = bits ? pos0 + j + __ffs(bits) - 1
-                              : (nl ? pos0 + 16 + __ffs(nl) - 1 : kLongEnd);
-      pairs[rank - w0] = (pos0 + j) | (e << 16);
-    }
+    if (rank - w0 < kWaveStarts) starts[rank - w0] = (uint16_t)(pos0 + j);
     ++rank;
     m &= m - 1;
   }
 }
 
+// Word-end bitmap of a wave's staged text: bit p set when byte p of the staged text (16-byte
+// prefix, the stripe) is the last byte of a word; kEndWords words, the tail always zero.
+constexpr uint32_t kEndWords = (kStripeText + 31) / 32 + 1;
+
 // One workgroup of BLOCK threads scans a contiguous range of STAGE-byte stages; wave v takes
 // a contiguous run of the range's 1 KiB stripes and runs on its own, with no workgroup barrier
 // until the range ends. Per stripe: classify 16 bytes per lane (plus the byte before the
-// stripe), word start / end masks, a wave-wide compaction of the (start, end) pairs, and up to
-// two tokens per lane per round: counted in the dictionary, or written as a record to its
-// partition, or (longer than 16 bytes) counted in the global table.
+// stripe), word start / end masks, a wave-wide compaction of the word starts (with a bitmap of
+// the word ends beside it), and up to two tokens per lane per round: counted in the
+// dictionary, or written as a record to its partition, or (longer than 16 bytes) counted in the
+// global table.
 //
-// Records. Each partition's records of this workgroup go to the workgroup's own blocks of the
-// partition's arena region, in the order of a per-partition ticket taken with one LDS atomic:
-// ticket t is slot t mod 256 of the workgroup's (t / 256)-th block, block j * G + w of the
-// region (G workgroups, this one w). Lanes store their records straight to the arena, one
-// 16-byte store each; the lines of a block fill in L2 before they are written back. The lane
-// holding a block's last slot sets its fill to full; the workgroup sets the fill of each
-// partition's last, partial block when its range is done. A partition whose share of blocks
-// is used up sends the rest of its records to the global table.
+// Records. Each partition's records of this workgroup go to the workgroup's own blocks of that
+// partition, in the order of a per-partition ticket taken with one LDS atomic: ticket t is
+// slot t mod 256 of the workgroup's (t / 256)-th block. The arena is laid out workgroup-major:
+// block k = w * J + j of partition p (workgroup w, its j-th block, J per workgroup) sits at
+// arena block k * 256 + p, so the blocks a workgroup is filling lie side by side in one 1 MiB
+// span instead of at a large power-of-two stride (which mapped them to few cache sets and had
+// lines written back before they were full). Lanes store their records straight to the arena,
+// one 16-byte store each. The lane holding a block's last slot sets its fill to full; the
+// workgroup sets the fill of each partition's last, partial block when its range is done. A
+// partition whose share of blocks is used up sends the rest of its records to the global
+// table.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   constexpr int NW = BLOCK / 64;
@@ -716,16 +716,19 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   for (uint32_t i = tid; i < nd; i += BLOCK) s_cnt[i] = 0;
   for (uint32_t p = tid; p < kParts; p += BLOCK) s_tick[p] = 0;
   for (uint32_t i = tid; i < NW * kBndWords; i += BLOCK) (&s_bnd[0][0])[i] = 0;
+  for (uint32_t i = tid; i < NW * kWaveStarts; i += BLOCK) s_pairs[i] = 0;
   if (tid < 4) s_stat[tid] = 0;
   __syncthreads();
 
-  // This workgroup's j-th block of partition p is block j * G + w of region p (J = S / G
-  // blocks each).
+  // This workgroup's j-th block of partition p is block k = w * J + j (J = S / G blocks each).
   const uint32_t G = gridDim.x, w = blockIdx.x;
   const uint32_t J = P.S / G;
   uint8_t* const my_txt = s_txt + wv * kStripeText;
   uint32_t* const my_bnd = s_bnd[wv];
-  uint32_t* const my_pairs = s_pairs + wv * kWaveStarts;
+  // per wave: kWaveStarts 16-bit starts, then the word-end bitmap
+  uint16_t* const my_starts = (uint16_t*)(s_pairs + wv * kWaveStarts);
+  uint32_t* const my_ends = s_pairs + wv * kWaveStarts + kWaveStarts / 2;
+  static_assert(kWaveStarts / 2 + kEndWords <= kWaveStarts, "starts and ends fit a wave's list");
 
   auto insert_record = [&](const uint4 r) {
     const uint64_t lo = (uint64_t)r.x | ((uint64_t)r.y << 32);
@@ -762,44 +765,74 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     }
   };
 
-  // A record of partition p: the next ticket of p places it in the workgroup's blocks; the
-  // lane that fills a block's last slot marks the block full.
-  auto place = [&](uint32_t p, const uint4 rec) {
-    const uint32_t t = atomicAdd(&s_tick[p], 1u);
-    const uint32_t j = t / kBlockRec, at = t % kBlockRec;
-    if (j < J) {
-      const uint64_t gb = (uint64_t)p * P.R + (uint64_t)j * G + w;
-      P.arena[gb * kBlockRec + at] = rec;
-      if (at == kBlockRec - 1) P.fill[gb] = (uint16_t)kBlockRec;
-    } else {
-      ++direct;  // the partition's share of blocks is used up
-      insert_record(rec);
-    }
-  };
-
-  // One round: pairs t and t + 64 of this wave's list (t = lane), for those below nw. A token
-  // that misses the dictionary becomes a record of its partition.
+  // One round: starts t and t + 64 of this wave's list (t = lane), for those below nw. A word's
+  // end is the first set bit of the end bitmap at or after its start. Both tokens go through
+  // each step together, so their LDS reads overlap. A token that misses the dictionary becomes
+  // a record of its partition.
   auto token_round = [&](uint32_t nw, int64_t p0) {
-    const uint32_t ta = lane, tb = lane + 64;
-    const uint32_t pra = ta < nw ? my_pairs[ta] : 0u, prb = tb < nw ? my_pairs[tb] : 0u;
-    const uint32_t sa = pra & 0xffffu, ea = pra >> 16, sb = prb & 0xffffu, eb = prb >> 16;
-    const bool longa = ta < nw && (ea == kLongEnd || ea - sa >= 16);
-    const bool longb = tb < nw && (eb == kLongEnd || eb - sb >= 16);
-    const bool fa = ta < nw && !longa, fb = tb < nw && !longb;
-    if (longa) long_token(p0, sa, ea);
-    if (longb) long_token(p0, sb, eb);
-    uint64_t loa = 0, hia = 0, lob = 0, hib = 0;
-    if (fa) pack_word(my_txt, sa, ea - sa + 1, &loa, &hia);
-    if (fb) pack_word(my_txt, sb, eb - sb + 1, &lob, &hib);
-    const uint32_t ha = word_hash32(loa, hia), hb = word_hash32(lob, hib);
-    const int ia = fa ? dict_find(s_disp, s_dslot, s_keys, loa, hia, ha) : -1;
-    const int ib = fb ? dict_find(s_disp, s_dslot, s_keys, lob, hib, hb) : -1;
-    if (ia >= 0) atomicAdd(&s_cnt[ia], 1u);
-    if (ib >= 0) atomicAdd(&s_cnt[ib], 1u);
-    const bool ma = fa && ia < 0, mb = fb && ib < 0;
-    if (ma) place(part_of(ha), key4(loa, hia));
-    if (mb) place(part_of(hb), key4(lob, hib));
-    spilled += (ma ? 1u : 0u) + (mb ? 1u : 0u);
+    uint32_t s2[2], n2[2], e0[2], e1[2];
+    bool f2[2];
+    // (list entries past nw are stale starts of earlier rounds: in range, not counted)
+#pragma unroll
+    for (int x = 0; x < 2; ++x) s2[x] = my_starts[lane + 64 * x];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      e0[x] = my_ends[s2[x] >> 5];
+      e1[x] = my_ends[(s2[x] >> 5) + 1];
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      n2[x] = __ffs(__builtin_amdgcn_alignbit(e1[x], e0[x], s2[x] & 31));  // 0: no end in 32
+      f2[x] = lane + 64 * x < nw && n2[x] - 1 < 16u;
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+      if (lane + 64 * x < nw && !f2[x])
+        long_token(p0, s2[x], n2[x] ? s2[x] + n2[x] - 1 : kLongEnd);
+    uint64_t lo2[2], hi2[2];
+    uint32_t h2[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      pack_word(my_txt, s2[x], f2[x] ? n2[x] : 1u, &lo2[x], &hi2[x]);
+      h2[x] = word_hash32(lo2[x], hi2[x]);
+    }
+    uint32_t d2[2], i2[2];
+    uint4 k2[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) d2[x] = s_disp[dict_group(h2[x])];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) i2[x] = s_dslot[dict_slot(h2[x], d2[x])];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) k2[x] = s_keys[i2[x]];
+    bool m2[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const uint4 want = key4(lo2[x], hi2[x]);
+      const bool hit = k2[x].x == want.x && k2[x].y == want.y && k2[x].z == want.z &&
+                       k2[x].w == want.w;
+      if (f2[x] && hit) atomicAdd(&s_cnt[i2[x]], 1u);
+      m2[x] = f2[x] && !hit;
+    }
+    uint32_t t2[2] = {0u, 0u};
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+      if (m2[x]) t2[x] = atomicAdd(&s_tick[part_of(h2[x])], 1u);
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      if (m2[x]) {
+        const uint32_t p = part_of(h2[x]), j = t2[x] / kBlockRec, at = t2[x] % kBlockRec;
+        const uint4 rec = key4(lo2[x], hi2[x]);
+        if (j < J) {
+          const uint64_t k = (uint64_t)w * J + j;
+          P.arena[(k * kParts + p) * kBlockRec + at] = rec;
+          if (at == kBlockRec - 1) P.fill[(uint64_t)p * P.S + k] = (uint16_t)kBlockRec;
+        } else {
+          ++direct;  // the partition's share of blocks is used up
+          insert_record(rec);
+        }
+      }
+    }
+    spilled += (m2[0] ? 1u : 0u) + (m2[1] ? 1u : 0u);
   };
 
   // Wave wv scans its own contiguous run of nsw stripes of the workgroup's range. The word
@@ -897,8 +930,6 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
         (uint32_t)__builtin_amdgcn_update_dpp(1, (int)(w16 & 1u), 0x130, 0xf, 0xf, false);
     uint32_t start16 = w16 & (~((w16 << 1) | prev) | bnd16) & 0xffffu;
     const uint32_t last16 = w16 & (~((w16 >> 1) | (nxt << 15)) | (bnd16 >> 1) | (bnext << 15)) & 0xffffu;
-    const uint32_t nl =
-        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)last16, 0x130, 0xf, 0xf, false);
     // lane 63's last word, when it runs to the stripe's end, is left for the next stripe
     uint32_t ndef_j = 16;
     if (lane == 63 && start16) {
@@ -908,14 +939,13 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
         start16 &= ~(1u << j);
       }
     }
-    // the previous stripe's last word: it ends at the prefix's last byte unless it runs on
-    // into lane 0 (then at lane 0's first end, or it is longer than 16 bytes)
-    uint32_t def_pair = 0;
-    if (def) {
-      const uint32_t w0b = (uint32_t)__builtin_amdgcn_readfirstlane((int)(w16 & ~start16 & 1u));
-      const uint32_t l0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)last16);
-      const uint32_t e = w0b == 0 ? 15u : (l0 ? 16u + __builtin_ctz(l0) : kLongEnd);
-      def_pair = def_s | (e << 16);
+    // end bitmap: lane l's ends at half-word 1 + l; half-word 0 (the prefix) holds one end, at
+    // its last byte, when the previous stripe's last word stops there (lane 0's first byte does
+    // not continue it)
+    ((uint16_t*)my_ends)[1 + lane] = (uint16_t)last16;
+    if (lane == 0) {
+      const bool cont = (w16 & ~start16 & 1u) != 0;
+      ((uint16_t*)my_ends)[0] = (uint16_t)(def && !cont ? 0x8000u : 0u);
     }
 
     // ---- compaction and tokens, kWaveStarts at a time -------------------------------------
@@ -925,8 +955,8 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     tokens += n;
     for (uint32_t w0 = 0; w0 < n; w0 += kWaveStarts) {
-      if (extra && w0 == 0) my_pairs[0] = def_pair;
-      write_pairs(start16, last16, nl, incl - c + extra, w0, my_pairs);
+      if (extra && w0 == 0) my_starts[0] = (uint16_t)def_s;
+      write_starts16(start16, incl - c + extra, w0, my_starts);
       wave_sync();
       token_round(min(n - w0, kWaveStarts), p0 - 16);
       wave_sync();
@@ -948,7 +978,7 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   __syncthreads();
   if (tid < (int)kParts) {
     const uint32_t t = s_tick[tid], j = t / kBlockRec, at = t % kBlockRec;
-    if (at && j < J) P.fill[(uint64_t)tid * P.R + (uint64_t)j * G + w] = (uint16_t)at;
+    if (at && j < J) P.fill[(uint64_t)tid * P.S + (uint64_t)w * J + j] = (uint16_t)at;
   }
   for (uint32_t i = tid; i < nd; i += BLOCK) P.dict_part[(uint64_t)blockIdx.x * D + i] = s_cnt[i];
   if (spilled) atomicAdd(&s_stat[0], spilled);
@@ -1119,11 +1149,11 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
     if (v) atomicAdd(&s_dsum[c], (unsigned long long)v);
   }
 
-  // records of partition p: its own blocks of every pass-1 workgroup, then the blocks handed
-  // out past S; the non-empty ones are listed kWinBlocks at a time and read whole
-  const uint32_t nblk = P.S + min(P.cursor[p], P.R - P.S);
-  const uint4* region = P.arena + (uint64_t)p * P.R * kBlockRec;
-  const uint16_t* fills = P.fill + (uint64_t)p * P.R;
+  // records of partition p: blocks k < S (every pass-1 workgroup's share); the non-empty ones
+  // are listed kWinBlocks at a time and read whole. Block k is arena block k * 256 + p.
+  const uint32_t nblk = P.S;
+  const uint4* region = P.arena + (uint64_t)p * kBlockRec;
+  const uint16_t* fills = P.fill + (uint64_t)p * P.S;
   constexpr uint32_t kPerIter = BLOCK / kBlockRec;  // blocks per iteration
   static_assert(BLOCK % kBlockRec == 0, "whole blocks per iteration");
   // b_in is the same for a whole wave (a block is 4 waves): list reads and block addresses
@@ -1180,7 +1210,7 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
     auto load = [&](uint32_t e, uint4& vv, uint32_t& ff) {
       const uint32_t ee = e < nl ? e : 0u;
       ff = e < nl ? s_lfill[ee] : 0u;
-      vv = region[(uint64_t)(w0 + s_list[ee]) * kBlockRec + r_in];
+      vv = region[(uint64_t)(w0 + s_list[ee]) * (kParts * kBlockRec) + r_in];
     };
 #pragma unroll
     for (int jj = 0; jj < kDepth; ++jj)

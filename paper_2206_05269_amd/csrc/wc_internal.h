@@ -88,20 +88,18 @@ struct GlobalParams {
   uint32_t* dict_part;       // [map_grid][dict_cap] dictionary hits per pass-1 workgroup
   Slot* sample_table;        // [kSampleSlots]
   Header* sample_hdr;
-  uint32_t R;                // arena blocks per partition (kParts * R < 2^32)
   uint32_t reduce_entries;   // pass-2 LDS entries (distinct words of a partition, <= kRedSlots)
   uint32_t reduce_cap;       // entries used before further new words go to the global table
-  uint32_t S;                // static blocks per partition: block j * map_grid + w is the
-                             // j-th of pass-1 workgroup w; blocks [S, R) are handed out
-  uint4* arena;              // [kParts][R][kBlockRec] records
-  uint32_t* cursor;          // [kParts] blocks handed out past S per partition
-  uint16_t* fill;            // [kParts][R] records per block (zero before pass 1)
+  uint32_t S;                // blocks per partition (kParts * S < 2^32): block k = w * J + j is
+                             // the j-th of pass-1 workgroup w (J = S / map_grid)
+  uint4* arena;              // [S][kParts][kBlockRec] records: block k of partition p at k * kParts + p
+  uint16_t* fill;            // [kParts][S] records per block (zero before pass 1)
 };
 size_t global_map_dyn(uint32_t dict_cap);
 size_t global_reduce_dyn(uint32_t entries);
 hipError_t set_global_smem(uint32_t dict_cap, uint32_t reduce_entries);
 // Sample, dictionary, pass 1 (between events a and b when given) and pass 2. The sample
-// table, its header, the dictionary image, the cursors and the block fills must be zero.
+// table, its header, the dictionary image and the block fills must be zero.
 hipError_t launch_global(const GlobalParams& P, hipEvent_t a, hipEvent_t b, hipStream_t s);
 
 // per-document count (wc_docs.hip)
