@@ -163,6 +163,7 @@ struct DocLayout {
   uint64_t* doc_ptr;
   uint64_t* doc_len;
   Slot* arena;
+  uint64_t* over_docs;
   uint64_t total;
 };
 
@@ -194,6 +195,7 @@ void layout_docs(uint64_t len, uint64_t n_docs, const wc_opts* o, void* ws, DocL
   L->doc_ptr = B.take<uint64_t>(std::max<uint64_t>(n_docs, 1) * 8);
   L->doc_len = B.take<uint64_t>(std::max<uint64_t>(n_docs, 1) * 8);
   L->arena = B.take<Slot>(L->arena_slots * sizeof(Slot));
+  L->over_docs = B.take<uint64_t>(std::max<uint64_t>(n_docs, 1) * 8);
   L->total = B.off;
 }
 
@@ -220,6 +222,7 @@ DocParams doc_params(const DocLayout& L, const wc_opts* o, uint32_t lds, uint32_
   P.cap_e = L.cap_e;
   P.cap_b = L.cap_b;
   P.arena = L.arena;
+  P.over_docs = L.over_docs;
   P.arena_slots = L.arena_slots;
   P.key_mask = key_mask_of(o);
   P.count_bias = o->debug_count_bias;
@@ -351,7 +354,7 @@ hipError_t ensure_smem_attr() {
     hipError_t e = set_count_smem(512, 160 * 1024 - 40 * 1024);
     if (e == hipSuccess) e = set_count_smem(256, 160 * 1024 - 24 * 1024);
     if (e == hipSuccess) e = set_global_smem(kDictMax, kReduceLds);
-    if (e == hipSuccess) e = set_doc_smem((size_t)kDocLds * 24);
+    if (e == hipSuccess) e = set_doc_smem(doc_dyn(kDocLds));
     return e;
   }();
   return once;
@@ -448,7 +451,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
     uint32_t grid = tu.grid ? tu.grid : (uint32_t)device_cus();
     DocParams P = doc_params(D, opts, lds, tu.pct, tu.chunk);
     if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
-    HIPCHK(launch_docs(P, grid, (size_t)lds * 24, s));
+    HIPCHK(launch_docs(P, grid, doc_dyn(lds), s));
     if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
     Header h;
     HIPCHK(hipMemcpyAsync(&h, D.hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
@@ -1068,7 +1071,7 @@ wc_status wc_batch_run(wc_batch* b, const uint8_t* d_corpus, uint64_t corpus_len
     hipError_t e = hipMemcpyAsync(b->D.task, b->h_task, sizeof(DocTask), hipMemcpyHostToDevice,
                                   b->bs);
     if (e == hipSuccess) e = launch_fill_zero(b->D.hdr, sizeof(Header), b->bs);
-    if (e == hipSuccess) e = launch_docs(P, b->grid, (size_t)b->lds * 24, b->bs);
+    if (e == hipSuccess) e = launch_docs(P, b->grid, doc_dyn(b->lds), b->bs);
     if (e == hipSuccess)
       e = hipMemcpyAsync(b->h_hdr, b->D.hdr, sizeof(Header), hipMemcpyDeviceToHost, b->bs);
     hipGraph_t g = nullptr;

@@ -64,7 +64,8 @@ struct Header {
   // counted straight in the global table, dictionary words, (unused), records pass 2 could
   // not sum in LDS
   uint64_t stat[5];
-  uint64_t pad[2];
+  uint64_t over_n;        // per-document output: documents queued for the second pass
+  uint64_t over_next;     // per-document output: second-pass queue cursor
 };
 static_assert(sizeof(Header) == 128, "header layout");
 

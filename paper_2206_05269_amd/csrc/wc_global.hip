@@ -21,6 +21,7 @@
 // Words longer than 16 bytes, and anything a bounded structure cannot take (an exhausted arena
 // region, a full pass-2 table), go to the global table directly.
 #include "wc_internal.h"
+#include "wc_stripe.h"
 
 namespace wc {
 
@@ -50,10 +51,6 @@ WC_DEV uint32_t dict_field(uint32_t h, uint32_t sel) {
 WC_DEV uint32_t dict_slot(uint32_t h, uint32_t d) {
   const uint32_t g = dict_group(h);
   return ((g & (kDictRegions - 1)) << 8) | ((dict_field(h, (d >> 8) & 1u) ^ d) & 0xffu);
-}
-
-WC_DEV uint4 key4(uint64_t lo, uint64_t hi) {
-  return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
 }
 
 template <bool kPerDoc>
@@ -187,84 +184,6 @@ WC_DEV void sample_insert(Slot* tab, uint64_t mask, uint64_t lo, uint64_t hi, ui
       }
     }
   }
-}
-
-// 16 bytes of the logical text at p; bytes outside [0, len) read as spaces.
-WC_DEV uint4 load_text16(const uint8_t* corpus, uint64_t len, int64_t p) {
-  if (p >= 0 && p + 16 <= (int64_t)len) return load_stream16(corpus + p);
-  uint32_t w[4] = {0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u};
-  for (int j = 0; j < 16; ++j) {
-    int64_t q = p + j;
-    if (q >= 0 && q < (int64_t)len) {
-      uint32_t b = corpus[q];
-      w[j >> 2] = (w[j >> 2] & ~(0xffu << ((j & 3) * 8))) | (b << ((j & 3) * 8));
-    }
-  }
-  return make_uint4(w[0], w[1], w[2], w[3]);
-}
-
-// Folded bytes and 16-bit word mask of 16 text bytes.
-WC_DEV uint4 classify16(uint4 v, uint32_t* w16) {
-  uint32_t f0, f1, f2, f3;
-  uint4 g;
-  g.x = fold_classify4(v.x, &f0);
-  g.y = fold_classify4(v.y, &f1);
-  g.z = fold_classify4(v.z, &f2);
-  g.w = fold_classify4(v.w, &f3);
-  *w16 = movemask4(f0) | (movemask4(f1) << 4) | (movemask4(f2) << 8) | (movemask4(f3) << 12);
-  return g;
-}
-
-// keep the bits of 16 bytes at logical position p that lie in [a, b)
-WC_DEV uint32_t cut16(uint32_t w16, int64_t p, int64_t a, int64_t b) {
-  if (p >= a && p + 16 <= b) return w16;
-  int64_t lo_cut = a - p, hi_cut = b - p;
-  uint32_t m = 0xffffu;
-  if (lo_cut > 0) m &= lo_cut >= 16 ? 0u : (0xffffu << lo_cut) & 0xffffu;
-  if (hi_cut < 16) m &= hi_cut <= 0 ? 0u : (0xffffu >> (16 - hi_cut));
-  return w16 & m;
-}
-
-// Packed bytes of the word at byte s of the staged text (1 <= wl <= 16 bytes, all staged):
-// five dword reads, byte alignment, and the bytes past the word cleared.
-WC_DEV void pack_word(const uint8_t* s_txt, uint32_t s, uint32_t wl, uint64_t* lo, uint64_t* hi) {
-  const uint32_t* tw = (const uint32_t*)s_txt;
-  const uint32_t di = s >> 2, sh = s & 3;
-  const uint32_t d0 = tw[di], d1 = tw[di + 1], d2 = tw[di + 2], d3 = tw[di + 3], d4 = tw[di + 4];
-  uint64_t a = (uint64_t)__builtin_amdgcn_alignbyte(d1, d0, sh) |
-               ((uint64_t)__builtin_amdgcn_alignbyte(d2, d1, sh) << 32);
-  uint64_t b = (uint64_t)__builtin_amdgcn_alignbyte(d3, d2, sh) |
-               ((uint64_t)__builtin_amdgcn_alignbyte(d4, d3, sh) << 32);
-  const uint32_t ka = wl < 8 ? 64 - 8 * wl : 0u;    // bits of a past the word
-  const uint32_t kb = wl < 16 ? 128 - 8 * wl : 0u;  // bits of b past the word (>= 64: all)
-  a = (a << ka) >> ka;
-  b = kb >= 64 ? 0ull : (b << kb) >> kb;
-  *lo = a;
-  *hi = b;
-}
-
-// Inclusive prefix sum over the 64 lanes of a wave: shifts within each 16-lane row, then the
-// row broadcasts of lanes 15 and 31 (lanes whose source is outside the row, and rows the mask
-// leaves out, add 0).
-WC_DEV uint32_t wave_incl_scan(uint32_t x) {
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  // opaque to the optimiser: a caller that subtracts its own term must not have the sum
-  // rebuilt from the shifted partials (which keeps each shift a separate move)
-  __asm__ volatile("" : "+v"(x));
-  return x;
-}
-
-// Orders this wave's LDS accesses around the point in the compiler (the hardware keeps one
-// wave's LDS operations in order).
-WC_DEV void wave_sync() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_wave_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // Positions (tid * 16 + bit) of the starts in mask m whose ranks, counted from `rank`, fall
@@ -622,43 +541,12 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
 // pass 1
 // ---------------------------------------------------------------------------------------
 constexpr int kMapWaves = kMapBlock / 64;
-constexpr uint32_t kLongEnd = 0x7ffu;                    // word end not within the staged bytes
-constexpr uint32_t kBndWords = kStripeText / 32 + 1;     // document-start bits of a stripe
 
 size_t global_map_dyn(uint32_t dict_cap) {
   return (size_t)kMapWaves * kStripeText +
          (size_t)(kDispBuckets + kDictSlots) * 2 + (size_t)(dict_cap + 1) * 16 + (size_t)dict_cap * 4 +
          (size_t)kMapWaves * kWaveStarts * 4;
 }
-
-// 4 bytes of the logical text at p (p + base alignment keeps them in one aligned dword); bytes
-// outside [0, len) read as spaces.
-WC_DEV uint32_t load_text4(const uint8_t* corpus, uint64_t len, int64_t p) {
-  if (p >= 0 && p + 4 <= (int64_t)len) return *(const uint32_t*)(corpus + p);
-  uint32_t w = 0x20202020u;
-  for (int j = 0; j < 4; ++j) {
-    const int64_t q = p + j;
-    if (q >= 0 && q < (int64_t)len)
-      w = (w & ~(0xffu << (8 * j))) | ((uint32_t)corpus[q] << (8 * j));
-  }
-  return w;
-}
-
-// Positions of the word starts in this lane's 16 bytes (after the 16-byte prefix), in text
-// order, for the ranks in [w0, w0 + kWaveStarts).
-WC_DEV void write_starts16(uint32_t m, uint32_t rank, uint32_t w0, uint16_t* starts) {
-  const uint32_t pos0 = 16 + (threadIdx.x & 63) * 16;
-  while (m) {
-    const uint32_t j = __ffs(m) - 1;
-    if (rank - w0 < kWaveStarts) starts[rank - w0] = (uint16_t)(pos0 + j);
-    ++rank;
-    m &= m - 1;
-  }
-}
-
-// Word-end bitmap of a wave's staged text: bit p set when byte p of the staged text (16-byte
-// prefix, the stripe) is the last byte of a word; kEndWords words, the tail always zero.
-constexpr uint32_t kEndWords = (kStripeText + 31) / 32 + 1;
 
 // One workgroup of BLOCK threads scans a contiguous range of STAGE-byte stages; wave v takes
 // a contiguous run of the range's 1 KiB stripes and runs on its own, with no workgroup barrier
@@ -989,118 +877,6 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     if (s_stat[0]) add64(&hdr->stat[0], s_stat[0]);
     if (s_stat[1]) add64(&hdr->stat[1], s_stat[1]);
   }
-}
-
-// ---------------------------------------------------------------------------------------
-// pass-2 LDS table: kRedSlots slots of (19-bit tag << 13 | entry) probed in groups of 4 (one
-// 16-byte read), and dense entries (key, count). A new word takes an entry, writes its key,
-// then claims an empty slot with a CAS; a reader that meets a claimed slot whose key is not
-// visible yet looks again next iteration. Two waves racing on the same new word may give it
-// two entries; both are added to the global table, which sums them.
-// ---------------------------------------------------------------------------------------
-struct RedTable {
-  uint32_t* slot;  // [kRedSlots], 0 = empty
-  uint4* key;      // [cap]
-  uint32_t* cnt;   // [cap]
-  uint32_t* n;     // entries handed out
-  uint32_t cap;
-};
-
-// Hash of a record for the pass-2 table (the word hash is useless here: its low 8 bits are the
-// partition's): the dwords folded with rotations and one multiply; the group is the top 11
-// bits, the tag 19 bits below them.
-WC_DEV uint32_t red_hash(const uint4 v) {
-  const uint32_t x = (v.x ^ __builtin_amdgcn_alignbit(v.y, v.y, 11)) +
-                     (v.z ^ __builtin_amdgcn_alignbit(v.w, v.w, 23));
-  return (x ^ (x >> 15)) * 0x9E3779B1u;
-}
-WC_DEV uint32_t red_tag(uint32_t h) { return ((h >> 2) & 0x7ffffu) | 1u; }
-WC_DEV uint32_t red_group(uint32_t h) { return h >> 21; }
-
-// The common case: the word has an entry, found by the first tag match of its home group.
-// Counts it and returns true; false sends the word to red_add.
-WC_DEV bool red_hit(const RedTable& T, const uint4 want, uint32_t h) {
-  const uint32_t tag = red_tag(h);
-  const uint4 s4 = ((const uint4*)T.slot)[red_group(h)];
-  const uint32_t e = (s4.x >> 13) == tag   ? s4.x
-                     : (s4.y >> 13) == tag ? s4.y
-                     : (s4.z >> 13) == tag ? s4.z
-                     : (s4.w >> 13) == tag ? s4.w
-                                           : 0u;
-  if (e == 0) return false;
-  const uint32_t idx = e & 0x1fffu;
-  const uint4 k = T.key[idx];
-  if (k.x != want.x || k.y != want.y || k.z != want.z || k.w != want.w) return false;
-  atomicAdd(&T.cnt[idx], 1u);
-  return true;
-}
-
-// Add one occurrence. Returns false when the word has no entry and none can be made (entries
-// exhausted or 16 groups probed): the caller counts it in the global table.
-WC_DEV bool red_add(const RedTable& T, uint64_t lo, uint64_t hi, uint32_t h) {
-  constexpr uint32_t kGroups = kRedSlots / 4;
-  constexpr uint32_t kNoEntry = 0xffffffffu;
-  const uint32_t tag = red_tag(h);
-  uint32_t g = red_group(h);
-  static_assert(kGroups == 2048, "group index takes the hash's top 11 bits");
-  const uint4 want = key4(lo, hi);
-  uint32_t mine = kNoEntry, probe = 0, waits = 0;
-  bool active = true, ok = false;
-  while (__any(active)) {
-    if (active) {
-      const uint4 s4 = ((const uint4*)T.slot)[g];
-      const uint32_t e[4] = {s4.x, s4.y, s4.z, s4.w};
-      bool found = false, wait = false;
-      int free_j = -1;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (found) continue;
-        if ((e[j] >> 13) == tag) {
-          const uint32_t idx = e[j] & 0x1fffu;
-          const uint4 k = T.key[idx];
-          if (k.x == want.x && k.y == want.y && k.z == want.z && k.w == want.w) {
-            atomicAdd(&T.cnt[idx], 1u);
-            found = true;
-          } else if ((k.x | k.y) == 0) {
-            wait = true;  // claimed, key not visible yet
-          }
-        } else if (e[j] == 0 && free_j < 0) {
-          free_j = j;
-        }
-      }
-      if (found) {
-        ok = true;
-        active = false;
-      } else if (wait) {
-        // look at this group again. A key is written before its slot is claimed, so a claimed
-        // slot shows a zero key only for a zero record, which no word makes: give up on it
-        if (++waits >= 4096) active = false;
-      } else if (free_j >= 0) {
-        if (mine == kNoEntry) {
-          const uint32_t m = atomicAdd(T.n, 1u);
-          if (m < T.cap) {
-            mine = m;
-            T.key[m] = want;
-          } else {
-            active = false;  // entries exhausted
-          }
-        }
-        if (active) {
-          const uint32_t prev = atomicCAS(&T.slot[g * 4 + free_j], 0u, (tag << 13) | mine);
-          if (prev == 0) {
-            atomicAdd(&T.cnt[mine], 1u);
-            ok = true;
-            active = false;
-          }  // else the slot was taken: look at this group again
-        }
-      } else {
-        g = (g + 1) & (kGroups - 1);
-        if (++probe >= 16) active = false;
-      }
-    }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  }
-  return ok;
 }
 
 // ---------------------------------------------------------------------------------------

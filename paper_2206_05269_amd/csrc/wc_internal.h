@@ -106,7 +106,7 @@ hipError_t launch_global(const GlobalParams& P, hipEvent_t a, hipEvent_t b, hipS
 constexpr uint64_t kWin = 64 * 1024;   // default bytes per work item window
 constexpr uint64_t kMinWin = 16 * 1024;
 constexpr uint32_t kDocW = 256;        // documents per sub-window
-constexpr uint32_t kDocLds = 4096;     // LDS table entries (24 bytes each)
+constexpr uint32_t kDocLds = 4096;     // LDS table entries (20 bytes each, beside 8192 slots)
 
 struct DocTask {           // device-resident: every size the per-document kernels read
   const uint8_t* corpus;
@@ -133,10 +133,12 @@ struct DocParams {
   uint64_t* doc_len;       // [n_docs]
   uint64_t cap_e, cap_b;
   Slot* arena;             // private tables of large documents
+  uint64_t* over_docs;     // [n_docs] documents for the second pass (| kTop: tokens not counted)
   uint64_t arena_slots;
   uint64_t key_mask;
   uint64_t count_bias;     // added to every exported count (debug; 0 normally)
 };
+size_t doc_dyn(uint32_t entries);  // dynamic LDS of the document kernel
 hipError_t set_doc_smem(size_t dyn);
 hipError_t launch_docs(const DocParams& P, uint32_t grid, size_t dyn, hipStream_t s);
 
