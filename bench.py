@@ -586,6 +586,7 @@ def batched_docs_per_s(steps: int, warmup: int, plain_docs: int):
     torch.cuda.synchronize()
     dt_b = (time.perf_counter() - t0) / steps
     entries = r.n_entries
+    recounted = r.stats["docs_recounted"]
     b.close()
     # plain: one launch (wc_count, global table of that document) per document
     off = c.offsets.cpu().numpy()
@@ -603,13 +604,13 @@ def batched_docs_per_s(steps: int, warmup: int, plain_docs: int):
     torch.cuda.synchronize()
     dt_p = (time.perf_counter() - t0) / m
     res = {"workload": name, "docs": n_docs, "bytes": B, "tokens": c.n_tokens,
-           "doc_word_pairs": entries,
+           "doc_word_pairs": entries, "docs_recounted": recounted,
            "batched_docs_per_s": round(n_docs / dt_b, 1), "batched_ms": round(dt_b * 1e3, 3),
            "batched_GBps": round(B / dt_b / 1e9, 2),
            "plain_docs_per_s": round(1.0 / dt_p, 1), "plain_sample_docs": m,
            "speedup": round((n_docs / dt_b) * dt_p, 1),
            "tuning": {"chunk_bytes": tu.chunk_bytes, "lds_entries": tu.lds_entries,
-                      "relief_load_pct": tu.lds_load_pct, "calibration_docs": cal,
+                      "lds_load_pct": tu.lds_load_pct, "calibration_docs": cal,
                       "tune_s": round(t_tune, 1)}}
     log(f"batched {res['batched_docs_per_s']} docs/s vs plain {res['plain_docs_per_s']} docs/s")
     return res

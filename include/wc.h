@@ -88,7 +88,9 @@ typedef struct wc_tuning {
   uint32_t lds_entries;   /* LDS table entries per workgroup, power of two, 256..4096 */
   uint32_t flush_policy;  /* WC_FLUSH_ALL or WC_FLUSH_BYPASS */
   uint32_t grid_blocks;   /* workgroups in the count launch (0 = 2 per CU) */
-  uint32_t lds_load_pct;  /* LDS table load at which it is flushed / relieved (0 = default) */
+  uint32_t lds_load_pct;  /* LDS table load at which it is flushed (one-pass kernel) or at
+                             which a document counts as overflowed (document-centric kernel:
+                             it is then counted again with a private table); 0 = default */
   uint32_t chunk_bytes;   /* per-document mode: bytes per work item, power of two in
                              16 KiB..1 MiB (0 = 64 KiB) */
 } wc_tuning;
@@ -138,13 +140,16 @@ typedef struct wc_result {
   uint64_t* d_docs;          /* WC_PER_DOC: uint64[n_entries], else NULL */
   float kernel_ms;           /* WC_DEBUG_TIME: duration of the count (or merge) kernel */
   float total_ms;            /* WC_DEBUG_TIME: duration of the whole call on the device */
-  /* Per-call statistics of the two-pass global count (zero for the other paths):
+  /* Per-call statistics (zero where a path has none). Two-pass global count:
    * [0] tokens written as records to the hash partitions (words missing the dictionary),
    * [1] records pass 1 added straight to the global table because the workgroup's share of
    *     their partition's arena blocks was used up,
    * [2] dictionary words,
-   * [3] 0 (reserved),
-   * [4] records pass 2 could not sum in its LDS table (added to the global table). */
+   * [4] records pass 2 could not sum in its LDS table (added to the global table).
+   * Document-centric per-document count (the batch API, and wc_count in per-document mode for
+   * small documents):
+   * [3] documents counted again in the kernel's second pass, with a private table in device
+   *     memory, because their words did not fit the LDS table. */
   uint64_t stats[5];
 } wc_result;
 
@@ -364,7 +369,7 @@ wc_status wc_server_destroy(wc_server* s);
 
 /* Autotuner: time wc_count on a calibration sample (device-resident, as wc_count) for each
  * point of a small grid of launch tunings (per-document mode: work-item bytes x LDS entries x
- * relief load; global mode: LDS entries x flush load x flush policy) with HIP events on
+ * LDS load; global mode: LDS entries x flush load x flush policy) with HIP events on
  * `stream`, and return the
  * fastest in *best (its time per call in *best_ms). The workspace must hold
  * wc_autotune_plan() bytes. The sample's counts are not returned. Output and private-table

@@ -462,6 +462,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
     out->total_tokens = h.total_tokens;
     out->n_docs = n_docs;
     out->table_slots = std::max<uint64_t>(h.arena_next, D.arena_slots);
+    out->stats[3] = h.over_n;
     out->count_bytes = opts->count_bytes;
     out->mode = WC_PER_DOC;
     out->d_word_offsets = D.woff;
@@ -1095,6 +1096,7 @@ wc_status wc_batch_run(wc_batch* b, const uint8_t* d_corpus, uint64_t corpus_len
   out->total_tokens = h.total_tokens;
   out->n_docs = n_docs;
   out->table_slots = std::max<uint64_t>(h.arena_next, b->D.arena_slots);
+  out->stats[3] = h.over_n;
   out->count_bytes = b->opts.count_bytes;
   out->mode = WC_PER_DOC;
   out->d_word_offsets = b->D.woff;

@@ -19,12 +19,12 @@
 // entry gives it its (entry, byte) place inside its document, so every document's entries
 // and word bytes are contiguous and the word offsets stay a valid CSR over the whole output.
 //
-// Overflowed documents are counted again, one at a time, by the whole workgroup: the LDS table
-// first, then a private open-addressing table in device memory (taken from an arena, cleared
-// by the workgroup, sized from the document's length) for the words that find no room; the
-// LDS entries are then added to the private table, which is compacted into the output. A
-// document longer than the window is always the last of its item and goes to this path at
-// once.
+// A document longer than the window is always the last of its item; it is counted after the
+// others, alone, with the whole LDS table to itself. Documents that still overflow are queued
+// for a second launch, which counts each one with a whole workgroup: the LDS table first, then
+// a private open-addressing table in device memory (taken from an arena, cleared by the
+// workgroup, sized from the document's length) for the words that find no room; the LDS
+// entries are then added to the private table, which is compacted into the output.
 //
 // Every size the kernels need is read from a device-side task description, so a whole call
 // can be captured once in a HIP graph and replayed for other corpora.
@@ -122,6 +122,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   T.cnt = (uint32_t*)(T.key + E);
   T.n = &s_nent;
   T.cap = min(P.lds_cap, E);
+  T.stall = hdr;  // a word must never be both in the LDS table and in a private table
   for (uint32_t i = tid; i < kRedSlots; i += BLOCK) T.slot[i] = 0;
   for (uint32_t i = tid; i < E; i += BLOCK) {
     T.key[i] = make_uint4(0, 0, 0, 0);
@@ -145,9 +146,9 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   // token counts in the LDS table under its document, or marks the document as overflowed
   // (tokens of an overflowed document are not counted further). Recount: [A, B) is one
   // document; every token counts in the LDS table, else in the document's private table.
-  // `count_tokens`: add the tokens to the call's total (each token is added once).
+  // The first pass adds the tokens to the call's total.
   constexpr bool recount = kRecount;
-  auto scan = [&](int64_t A, int64_t B, uint32_t nd, bool count_tokens) {
+  auto scan = [&](int64_t A, int64_t B, uint32_t nd) {
     const int64_t k0 = (A - base_off) / (int64_t)kStripe;
     const int64_t k1 = (B - base_off + (int64_t)kStripe - 1) / (int64_t)kStripe;
     const int64_t per = (k1 - k0 + NW - 1) / NW;
@@ -159,22 +160,22 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
     Slot* const priv = pok ? P.arena + s_pbase : nullptr;
     const uint64_t pmask = pok ? (uint64_t)s_pslots - 1 : 0;
 
-    // one token (lo, hi) of document r, all lanes that call it together
+    // a short word (lo, hi) of document r that found no room in the LDS table
+    auto overflow = [&](uint64_t lo, uint64_t hi, uint32_t r) {
+      if (!recount) {
+        s_over[r] = 1;
+      } else if (pok) {
+        table_insert<false>(priv, pmask, finish_key(fnv_packed(lo, hi, packed_len(lo, hi)), P.key_mask),
+                            short_id(lo, hi, 0), 1, hdr, ~0ull);
+      }
+    };
+    // one short word (lo, hi) of document r, all lanes that call it together
     auto count_short = [&](uint64_t lo, uint64_t hi, uint32_t r) {
       if (!recount && s_over[r]) return;
       const uint64_t hr = recount ? hi : hi_with_doc(hi, r);
       const uint4 key = key4(lo, hr);
       const uint32_t h = red_hash(key);
-      bool ok = red_hit(T, key, h);
-      if (!ok) ok = red_add(T, lo, hr, h);
-      if (!ok) {
-        if (!recount) {
-          s_over[r] = 1;
-        } else if (pok) {
-          table_insert<false>(priv, pmask, finish_key(fnv_packed(lo, hi, packed_len(lo, hi)), P.key_mask),
-                              short_id(lo, hi, 0), 1, hdr, ~0ull);
-        }
-      }
+      if (!red_hit(T, key, h) && !red_add(T, lo, hr, h)) overflow(lo, hi, r);
     };
     // a word whose end is not in the staged bytes, or longer than 16 bytes: from device memory
     // (limit: its end when known, else its document's end)
@@ -296,22 +297,65 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
         write_starts16(start16, incl - c + extra, w0, my_starts);
         wave_sync();
         const uint32_t nw = min(n - w0, kWaveStarts);
+        // both tokens of the lane: start, length (0: no end within 32 bytes), document
+        uint32_t s2[2], wl2[2], r2[2];
+        bool sh2[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          s2[x] = my_starts[lane + 64 * x];
+          const uint32_t q = s2[x] >> 5;
+          wl2[x] = __ffs(__builtin_amdgcn_alignbit(my_ends[q + 1], my_ends[q], s2[x] & 31));
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const bool act = lane + 64 * x < nw;
+          r2[x] = act ? (s2[x] < 16 ? def_r : doc_at(s2[x])) : 0u;
+          sh2[x] = act && wl2[x] - 1 < 16u;
+          if (act && !sh2[x]) {
+            const int64_t start = p0 - 16 + (int64_t)s2[x];
+            long_word(start, wl2[x] ? (uint64_t)(start + wl2[x]) : doc_end(r2[x]), r2[x]);
+          }
+          if (!recount && sh2[x] && s_over[r2[x]]) sh2[x] = false;  // recounted later
+        }
+        // short words: packed, keyed and looked up together (the common case: the key has an
+        // entry in its home group); the rest through the general insert, one at a time
+        uint64_t lo2[2], hi2[2];
+        uint4 key2[2];
+        uint32_t h2[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          pack_word(my_txt, s2[x], sh2[x] ? wl2[x] : 1u, &lo2[x], &hi2[x]);
+          key2[x] = key4(lo2[x], recount ? hi2[x] : hi_with_doc(hi2[x], r2[x]));
+          h2[x] = red_hash(key2[x]);
+        }
+        uint4 g2[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) g2[x] = ((const uint4*)T.slot)[red_group(h2[x])];
+        uint32_t e2[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const uint32_t tag = red_tag(h2[x]);
+          e2[x] = (g2[x].x >> 13) == tag   ? g2[x].x
+                  : (g2[x].y >> 13) == tag ? g2[x].y
+                  : (g2[x].z >> 13) == tag ? g2[x].z
+                  : (g2[x].w >> 13) == tag ? g2[x].w
+                                           : 0u;
+        }
+        uint4 k2[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) k2[x] = T.key[e2[x] & 0x1fffu];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const bool hit = sh2[x] && e2[x] && k2[x].x == key2[x].x && k2[x].y == key2[x].y &&
+                           k2[x].z == key2[x].z && k2[x].w == key2[x].w;
+          if (hit) atomicAdd(&T.cnt[e2[x] & 0x1fffu], 1u);
+          sh2[x] = sh2[x] && !hit;
+        }
 #pragma unroll 1
         for (int x = 0; x < 2; ++x) {
-          const uint32_t t = lane + 64 * x;
-          const uint32_t s = my_starts[t];
-          const uint32_t q = s >> 5;
-          const uint32_t wl = __ffs(__builtin_amdgcn_alignbit(my_ends[q + 1], my_ends[q], s & 31));
-          if (t < nw) {
-            const uint32_t r = s < 16 ? def_r : doc_at(s);
-            if (wl - 1 < 16u) {
-              uint64_t lo, hi;
-              pack_word(my_txt, s, wl, &lo, &hi);
-              count_short(lo, hi, r);
-            } else {
-              const int64_t start = p0 - 16 + (int64_t)s;
-              long_word(start, wl ? (uint64_t)(start + wl) : doc_end(r), r);
-            }
+          if (sh2[x]) {
+            const uint64_t hr = recount ? hi2[x] : hi_with_doc(hi2[x], r2[x]);
+            if (!red_add(T, lo2[x], hr, h2[x])) overflow(lo2[x], hi2[x], r2[x]);
           }
         }
         wave_sync();
@@ -329,7 +373,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       tokens += 1;
       if (lane == 0) long_word(stripe_pos(nsw) - 16 + (int64_t)def_s, doc_end(def_r), def_r);
     }
-    if (count_tokens && lane == 0 && tokens) atomicAdd(&s_tokens, (unsigned long long)tokens);
+    if (!recount && lane == 0 && tokens) atomicAdd(&s_tokens, (unsigned long long)tokens);
   };
 
   // ---- emission of the LDS entries of documents [0, nd) that did not overflow ------------
@@ -411,68 +455,12 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
     __syncthreads();
   };
 
-  // ---- compaction of the private table of document d into the output (all threads) -------
-  auto compact_private = [&](uint64_t d) {
-    const Slot* t = P.arena + s_pbase;
-    const uint32_t slots = s_pslots;
-    uint32_t n = 0, b = 0;
-    for (uint32_t i = tid; i < slots; i += BLOCK) {
-      const Slot sl = t[i];
-      if (sl.key) {
-        ++n;
-        b += (uint32_t)slot_word_len(sl);
-      }
-    }
-    uint32_t tn, tb;
-    block_excl_scan32<BLOCK>(n, s_tmp, &tn);
-    block_excl_scan32<BLOCK>(b, s_tmp, &tb);
-    if (tid == 0) {
-      const uint64_t old = atomicAdd((unsigned long long*)&hdr->out_cursor,
-                                     (unsigned long long)(((uint64_t)tn << 32) | tb));
-      s_e0 = old >> 32;
-      s_b0 = old & 0xffffffffull;
-      if (s_e0 + tn > P.cap_e || s_b0 + tb > P.cap_b) or32(&hdr->flags, kFlagWordCap);
-      P.doc_ptr[d] = s_e0;
-      P.doc_len[d] = tn;
-    }
-    __syncthreads();
-    const bool room = s_e0 + tn <= P.cap_e && s_b0 + tb <= P.cap_b;
-    uint64_t e_run = s_e0, b_run = s_b0;
-    for (uint32_t c0 = 0; c0 < slots; c0 += BLOCK) {
-      const uint32_t i = c0 + tid;
-      Slot sl;
-      sl.key = 0;
-      if (i < slots) sl = t[i];
-      const uint32_t wl = sl.key ? (uint32_t)slot_word_len(sl) : 0u;
-      uint32_t cn, cb;
-      const uint32_t en = block_excl_scan32<BLOCK>(sl.key ? 1u : 0u, s_tmp, &cn);
-      const uint32_t eb = block_excl_scan32<BLOCK>(wl, s_tmp, &cb);
-      if (sl.key && room) {
-        const uint64_t e = e_run + en, bp = b_run + eb;
-        P.word_offsets[e] = bp;
-        const uint64_t c = sl.cnt + P.count_bias;
-        if (P.count_bytes == 4) {
-          if (c > 0x7fffffffull) or32(&hdr->flags, kFlagCountOverflow);
-          ((int32_t*)P.counts)[e] = (int32_t)c;
-        } else {
-          ((int64_t*)P.counts)[e] = (int64_t)c;
-        }
-        P.docs[e] = d;
-        if (sl.w0 & kTop) {
-          const uint8_t* src = (const uint8_t*)(uintptr_t)(sl.w0 & ~kTop);
-          for (uint32_t q = 0; q < wl; ++q) P.words[bp + q] = (uint8_t)fold_byte(src[q]);
-        } else {
-          put_packed(P.words + bp, sl.w0, sl.w1 & ~kTop, wl);
-        }
-      }
-      e_run += cn;
-      b_run += cb;
-    }
-    __syncthreads();
-  };
-
   // ---- a document counted on its own: LDS table, then a private table ----------------------
-  auto recount_doc = [&](int64_t A, int64_t B, uint64_t d, bool count_tokens) {
+  // Once the LDS table is full a word goes to the private table, but in the round that fills
+  // it one lane may get the last entry for a word while another lane holding the same word is
+  // refused: a short word of the private table can also sit in the LDS table. Its private
+  // count is then added to the LDS entry and the private slot is left out of the output.
+  auto recount_doc = [&](int64_t A, int64_t B, uint64_t d) {
     if (tid == 0) {
       // a document of b bytes has at most b/2 + 1 distinct words: b + 2 slots keep a small
       // document's table at most half full; large documents get b/16 slots (natural text has
@@ -490,31 +478,105 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       }
       s_pbase = base;
       s_pslots = (uint32_t)slots;
+      s_dcur[0] = 0;
     }
     __syncthreads();
     const bool usable = s_pbase != ~0ull - 1;
-    if (usable) {
-      Slot* t = P.arena + s_pbase;
-      for (uint32_t i = tid; i < s_pslots; i += BLOCK) t[i] = Slot{0, 0, 0, 0};
+    const Slot* t = P.arena + (usable ? s_pbase : 0);
+    const uint32_t slots = usable ? s_pslots : 0u;
+    for (uint32_t i = tid; i < slots; i += BLOCK) P.arena[s_pbase + i] = Slot{0, 0, 0, 0};
+    __syncthreads();
+    if (A < B) scan(A, B, 1);
+    __syncthreads();
+    // the document's entries and word bytes: LDS entries with a count, private slots in use
+    const uint32_t ne = min(s_nent, T.cap);
+    uint64_t part = 0;
+    for (uint32_t i = tid; i < ne; i += BLOCK) {
+      if (!T.cnt[i]) continue;
+      const uint4 k = T.key[i];
+      part += (1ull << 32) | packed_len((uint64_t)k.x | ((uint64_t)k.y << 32),
+                                        (uint64_t)k.z | ((uint64_t)k.w << 32));
+    }
+    // LDS entry of a private slot's word, or -1
+    auto in_lds = [&](const Slot& sl) -> int {
+      if (sl.w0 & kTop) return -1;  // longer than 16 bytes: never in the LDS table
+      const uint4 k = key4(sl.w0, sl.w1 & ~kTop);
+      return red_find(T, k, red_hash(k));
+    };
+    for (uint32_t i = tid; i < slots; i += BLOCK) {
+      const Slot sl = t[i];
+      if (!sl.key) continue;
+      const int li = in_lds(sl);
+      if (li >= 0) atomicAdd(&T.cnt[li], (uint32_t)sl.cnt);
+      else part += (1ull << 32) | slot_word_len(sl);
+    }
+    if (part) atomicAdd(&s_dcur[0], (unsigned long long)part);
+    __syncthreads();
+    if (tid == 0) {
+      const uint64_t tot = s_dcur[0];
+      const uint64_t tn = tot >> 32, tb = tot & 0xffffffffull;
+      const uint64_t old = atomicAdd((unsigned long long*)&hdr->out_cursor, (unsigned long long)tot);
+      s_e0 = old >> 32;
+      s_b0 = old & 0xffffffffull;
+      if (s_e0 + tn > P.cap_e || s_b0 + tb > P.cap_b) or32(&hdr->flags, kFlagWordCap);
+      if (usable) {
+        P.doc_ptr[d] = s_e0;
+        P.doc_len[d] = tn;
+      }
+      s_dcur[1] = tot;
+      s_dcur[0] = 0;
     }
     __syncthreads();
-    if (A < B) scan(A, B, 1, count_tokens);
-    __syncthreads();
-    if (usable) {
-      const uint32_t ne = min(s_nent, T.cap);
+    const uint64_t tot = s_dcur[1];
+    const bool room = usable && s_e0 + (tot >> 32) <= P.cap_e && s_b0 + (tot & 0xffffffffull) <= P.cap_b;
+    auto put = [&](uint64_t lo, uint64_t hi, uint32_t wl, uint64_t cnt, const uint8_t* src) {
+      const uint64_t at = atomicAdd(&s_dcur[0], (1ull << 32) | wl);
+      const uint64_t e = s_e0 + (at >> 32), bp = s_b0 + (at & 0xffffffffull);
+      P.word_offsets[e] = bp;
+      const uint64_t c = cnt + P.count_bias;
+      if (P.count_bytes == 4) {
+        if (c > 0x7fffffffull) or32(&hdr->flags, kFlagCountOverflow);
+        ((int32_t*)P.counts)[e] = (int32_t)c;
+      } else {
+        ((int64_t*)P.counts)[e] = (int64_t)c;
+      }
+      P.docs[e] = d;
+      if (src) {
+        for (uint32_t q = 0; q < wl; ++q) P.words[bp + q] = (uint8_t)fold_byte(src[q]);
+      } else {
+        put_packed(P.words + bp, lo, hi, wl);
+      }
+    };
+    if (room) {
       for (uint32_t i = tid; i < ne; i += BLOCK) {
         const uint32_t c = T.cnt[i];
         if (!c) continue;
         const uint4 k = T.key[i];
         const uint64_t lo = (uint64_t)k.x | ((uint64_t)k.y << 32);
         const uint64_t hi = (uint64_t)k.z | ((uint64_t)k.w << 32);
-        table_insert<false>(P.arena + s_pbase, (uint64_t)s_pslots - 1,
-                            finish_key(fnv_packed(lo, hi, packed_len(lo, hi)), P.key_mask),
-                            short_id(lo, hi, 0), c, hdr, ~0ull);
+        put(lo, hi, packed_len(lo, hi), c, nullptr);
+      }
+      for (uint32_t i = tid; i < slots; i += BLOCK) {
+        const Slot sl = t[i];
+        if (!sl.key || in_lds(sl) >= 0) continue;
+        const bool lng = (sl.w0 & kTop) != 0;
+        put(sl.w0, sl.w1 & ~kTop, (uint32_t)slot_word_len(sl), sl.cnt,
+            lng ? (const uint8_t*)(uintptr_t)(sl.w0 & ~kTop) : nullptr);
       }
     }
     clear_table();
-    if (usable) compact_private(d);
+  };
+
+  // documents of [d0, d0 + nd) that overflowed go to the second pass (their tokens are
+  // already in the total)
+  auto queue_over = [&](uint32_t nd, uint64_t d0) {
+    for (uint32_t r = tid; r < nd; r += BLOCK) {
+      if (s_over[r]) {
+        const uint64_t q = atomicAdd((unsigned long long*)&hdr->over_n, 1ull);
+        P.over_docs[q] = d0 + r;
+      }
+    }
+    __syncthreads();
   };
 
   if constexpr (!kRecount) {
@@ -529,24 +591,35 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       const uint64_t db = min(P.win_doc[w + 1], n_docs);
       for (uint64_t d0 = da; d0 < db; d0 += kDocW) {
         const uint32_t nd = (uint32_t)min((uint64_t)kDocW, db - d0);
-        // a document longer than the window is the last of its item: it skips this pass
+        // a document longer than the window is the last of its item: it is counted alone
+        // after the others, with the whole LDS table to itself
         const bool big = offsets[d0 + nd] - offsets[d0 + nd - 1] > win;
+        const uint32_t ns = big ? nd - 1 : nd;
         for (uint32_t i = tid; i <= nd; i += BLOCK) s_doff[i] = offsets[d0 + i];
-        for (uint32_t i = tid; i < nd; i += BLOCK) s_over[i] = big && i == nd - 1 ? 1u : 0u;
+        for (uint32_t i = tid; i < nd; i += BLOCK) s_over[i] = 0;
         __syncthreads();
-        const int64_t A = (int64_t)s_doff[0];
-        const int64_t B = (int64_t)s_doff[big ? nd - 1 : nd];
-        if (A < B) scan(A, B, nd, true);
-        __syncthreads();
-        emit(nd, d0);
-        clear_table();
-        // overflowed documents go to the second pass (with kTop: its tokens are not counted
-        // yet)
-        for (uint32_t r = tid; r < nd; r += BLOCK) {
-          if (s_over[r]) {
-            const uint64_t q = atomicAdd((unsigned long long*)&hdr->over_n, 1ull);
-            P.over_docs[q] = (d0 + r) | (big && r == nd - 1 ? kTop : 0ull);
+        if (ns > 0) {
+          const int64_t A = (int64_t)s_doff[0], B = (int64_t)s_doff[ns];
+          if (A < B) scan(A, B, ns);
+          __syncthreads();
+          emit(ns, d0);
+          clear_table();
+          queue_over(ns, d0);
+        }
+        if (big) {
+          const uint64_t d = d0 + nd - 1;
+          __syncthreads();
+          if (tid == 0) {
+            s_doff[0] = offsets[d];
+            s_doff[1] = offsets[d + 1];
+            s_over[0] = 0;
           }
+          __syncthreads();
+          scan((int64_t)s_doff[0], (int64_t)s_doff[1], 1);
+          __syncthreads();
+          emit(1, d);
+          clear_table();
+          queue_over(1, d);
         }
       }
     }
@@ -559,8 +632,8 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       const uint64_t q = s_item;
       __syncthreads();
       if (q >= n_over) break;
-      const uint64_t e = P.over_docs[q], d = e & ~kTop;
-      recount_doc((int64_t)offsets[d], (int64_t)offsets[d + 1], d, (e & kTop) != 0);
+      const uint64_t d = P.over_docs[q];
+      recount_doc((int64_t)offsets[d], (int64_t)offsets[d + 1], d);
     }
   }
   if (tid == 0) add64(&hdr->total_tokens, s_tokens);

@@ -901,6 +901,7 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   T.cnt = (uint32_t*)(T.key + E);
   T.n = &s_nent;
   T.cap = P.reduce_cap < E ? P.reduce_cap : E;
+  T.stall = nullptr;  // a word the table gives up on is summed in the global table
   for (uint32_t i = tid; i < kRedSlots; i += BLOCK) T.slot[i] = 0;
   for (uint32_t i = tid; i < E; i += BLOCK) {
     T.key[i] = make_uint4(0, 0, 0, 0);

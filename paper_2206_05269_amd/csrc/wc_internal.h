@@ -133,7 +133,7 @@ struct DocParams {
   uint64_t* doc_len;       // [n_docs]
   uint64_t cap_e, cap_b;
   Slot* arena;             // private tables of large documents
-  uint64_t* over_docs;     // [n_docs] documents for the second pass (| kTop: tokens not counted)
+  uint64_t* over_docs;     // [n_docs] documents for the second pass
   uint64_t arena_slots;
   uint64_t key_mask;
   uint64_t count_bias;     // added to every exported count (debug; 0 normally)

@@ -19,6 +19,7 @@ WC_DEV uint4 key4(uint64_t lo, uint64_t hi) {
 WC_DEV uint4 load_text16(const uint8_t* corpus, uint64_t len, int64_t p) {
   if (p >= 0 && p + 16 <= (int64_t)len) return load_stream16(corpus + p);
   uint32_t w[4] = {0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u};
+#pragma unroll 1
   for (int j = 0; j < 16; ++j) {
     int64_t q = p + j;
     if (q >= 0 && q < (int64_t)len) {
@@ -137,6 +138,7 @@ struct RedTable {
   uint32_t* cnt;   // [cap]
   uint32_t* n;     // entries handed out
   uint32_t cap;
+  Header* stall;   // when set: a give-up on a key that never became visible fails the call
 };
 
 // Hash of a key for the table (independent of the 32-bit word hash, whose low 8 bits choose the
@@ -168,8 +170,35 @@ WC_DEV bool red_hit(const RedTable& T, const uint4 want, uint32_t h) {
   return true;
 }
 
+// Entry index of a key, or -1, in a table nobody is changing: the probe of red_add without
+// its claims (a group with an empty slot ends it: claimed slots of a group form a prefix).
+WC_DEV int red_find(const RedTable& T, const uint4 want, uint32_t h) {
+  constexpr uint32_t kGroups = kRedSlots / 4;
+  const uint32_t tag = red_tag(h);
+  uint32_t g = red_group(h);
+  for (int probe = 0; probe < 16; ++probe) {
+    const uint4 s4 = ((const uint4*)T.slot)[g];
+    const uint32_t e[4] = {s4.x, s4.y, s4.z, s4.w};
+    bool empty = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if ((e[j] >> 13) == tag) {
+        const uint32_t idx = e[j] & 0x1fffu;
+        const uint4 k = T.key[idx];
+        if (k.x == want.x && k.y == want.y && k.z == want.z && k.w == want.w) return (int)idx;
+      } else if (e[j] == 0) {
+        empty = true;
+      }
+    }
+    if (empty) return -1;
+    g = (g + 1) & (kGroups - 1);
+  }
+  return -1;
+}
+
 // Add one occurrence. Returns false when the word has no entry and none can be made (entries
-// exhausted or 16 groups probed): the caller counts it in the global table.
+// exhausted or 16 groups probed): the caller counts it elsewhere. New entries are handed out
+// with one atomic per wave on the entry count.
 WC_DEV bool red_add(const RedTable& T, uint64_t lo, uint64_t hi, uint32_t h) {
   constexpr uint32_t kGroups = kRedSlots / 4;
   constexpr uint32_t kNoEntry = 0xffffffffu;
@@ -177,14 +206,16 @@ WC_DEV bool red_add(const RedTable& T, uint64_t lo, uint64_t hi, uint32_t h) {
   uint32_t g = red_group(h);
   static_assert(kGroups == 2048, "group index takes the hash's top 11 bits");
   const uint4 want = key4(lo, hi);
+  const uint32_t lane = threadIdx.x & 63;
   uint32_t mine = kNoEntry, probe = 0, waits = 0;
   bool active = true, ok = false;
   while (__any(active)) {
+    bool claim = false;
+    int free_j = -1;
     if (active) {
       const uint4 s4 = ((const uint4*)T.slot)[g];
       const uint32_t e[4] = {s4.x, s4.y, s4.z, s4.w};
       bool found = false, wait = false;
-      int free_j = -1;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (found) continue;
@@ -207,29 +238,44 @@ WC_DEV bool red_add(const RedTable& T, uint64_t lo, uint64_t hi, uint32_t h) {
       } else if (wait) {
         // look at this group again. A key is written before its slot is claimed, so a claimed
         // slot shows a zero key only for a zero record, which no word makes: give up on it
-        if (++waits >= 4096) active = false;
+        if (++waits >= 4096) {
+          active = false;
+          if (T.stall) or32(&T.stall->flags, kFlagStall);
+        }
       } else if (free_j >= 0) {
-        if (mine == kNoEntry) {
-          const uint32_t m = atomicAdd(T.n, 1u);
-          if (m < T.cap) {
-            mine = m;
-            T.key[m] = want;
-          } else {
-            active = false;  // entries exhausted
-          }
-        }
-        if (active) {
-          const uint32_t prev = atomicCAS(&T.slot[g * 4 + free_j], 0u, (tag << 13) | mine);
-          if (prev == 0) {
-            atomicAdd(&T.cnt[mine], 1u);
-            ok = true;
-            active = false;
-          }  // else the slot was taken: look at this group again
-        }
+        claim = true;
       } else {
         g = (g + 1) & (kGroups - 1);
         if (++probe >= 16) active = false;
       }
+    }
+    // entries for the lanes that claim a slot for the first time: one atomic per wave
+    const bool need = claim && mine == kNoEntry;
+    const uint64_t nm = __ballot(need);
+    if (nm) {
+      const uint32_t leader = (uint32_t)__ffsll((unsigned long long)nm) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(T.n, (uint32_t)__popcll(nm));
+      base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
+      if (need) {
+        const uint32_t m =
+            base + __builtin_amdgcn_mbcnt_hi((uint32_t)(nm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nm, 0u));
+        if (m < T.cap) {
+          mine = m;
+          T.key[m] = want;
+        } else {
+          claim = false;
+          active = false;  // entries exhausted
+        }
+      }
+    }
+    if (claim) {
+      const uint32_t prev = atomicCAS(&T.slot[g * 4 + free_j], 0u, (tag << 13) | mine);
+      if (prev == 0) {
+        atomicAdd(&T.cnt[mine], 1u);
+        ok = true;
+        active = false;
+      }  // else the slot was taken: look at this group again
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }

@@ -199,10 +199,13 @@ class Table:
 
     @property
     def stats(self) -> dict:
-        """Per-call statistics of the two-pass global count (all zero on other paths)."""
+        """Per-call statistics: the two-pass global count's spilled records, records sent
+        straight to the global table, dictionary words and pass-2 overflow; the
+        document-centric kernel's documents counted again with a private table (zero where a
+        path has none)."""
         s = self.res.stats
         return {"spilled": int(s[0]), "arena_direct": int(s[1]), "dict_words": int(s[2]),
-                "reduce_overflow": int(s[4])}
+                "docs_recounted": int(s[3]), "reduce_overflow": int(s[4])}
 
     def word_offsets(self) -> torch.Tensor:
         return self._view(self.res.d_word_offsets, 8 * (self.n_entries + 1), torch.int64)
