@@ -577,6 +577,7 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   static_assert(kWaveStarts == 128, "a round takes two tokens per lane");
   extern __shared__ __align__(16) uint8_t s_dyn[];
   __shared__ uint32_t s_tick[kParts];  // records of each partition so far
+  __shared__ uint4 s_lenmask[17];       // byte masks of word lengths 0..16
   __shared__ uint32_t s_bnd[NW][kBndWords];
   __shared__ uint32_t s_stat[4];
 
@@ -603,6 +604,7 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   for (uint32_t i = tid; i <= nd; i += BLOCK) s_keys[i] = P.dict->keys[i];
   for (uint32_t i = tid; i < nd; i += BLOCK) s_cnt[i] = 0;
   for (uint32_t p = tid; p < kParts; p += BLOCK) s_tick[p] = 0;
+  init_len_masks(s_lenmask, tid, BLOCK);
   for (uint32_t i = tid; i < NW * kBndWords; i += BLOCK) (&s_bnd[0][0])[i] = 0;
   for (uint32_t i = tid; i < NW * kWaveStarts; i += BLOCK) s_pairs[i] = 0;
   if (tid < 4) s_stat[tid] = 0;
@@ -681,7 +683,7 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     uint32_t h2[2];
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
-      pack_word(my_txt, s2[x], f2[x] ? n2[x] : 1u, &lo2[x], &hi2[x]);
+      pack_word_lm(my_txt, s2[x], s_lenmask, f2[x] ? n2[x] : 1u, &lo2[x], &hi2[x]);
       h2[x] = word_hash32(lo2[x], hi2[x]);
     }
     uint32_t d2[2], i2[2];

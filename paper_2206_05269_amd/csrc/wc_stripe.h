@@ -70,6 +70,35 @@ WC_DEV void pack_word(const uint8_t* s_txt, uint32_t s, uint32_t wl, uint64_t* l
   *hi = b;
 }
 
+// Byte masks of the first n of 16 bytes, n = 0..16 (one uint4 each), for pack_word_lm.
+WC_DEV void init_len_masks(uint4* m, uint32_t tid, uint32_t nthreads) {
+  for (uint32_t n = tid; n <= 16; n += nthreads) {
+    uint32_t w[4];
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint32_t nb = n > 4 * k ? min(n - 4 * k, 4u) : 0u;
+      w[k] = nb >= 4 ? 0xffffffffu : (1u << (8 * nb)) - 1u;
+    }
+    m[n] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+// pack_word with the bytes past the word cleared by a mask read from the table of
+// init_len_masks (issued beside the text reads) instead of computed shifts.
+WC_DEV void pack_word_lm(const uint8_t* s_txt, uint32_t s, const uint4* lenmask, uint32_t wl,
+                         uint64_t* lo, uint64_t* hi) {
+  const uint32_t* tw = (const uint32_t*)s_txt;
+  const uint32_t di = s >> 2, sh = s & 3;
+  const uint32_t d0 = tw[di], d1 = tw[di + 1], d2 = tw[di + 2], d3 = tw[di + 3], d4 = tw[di + 4];
+  const uint4 m = lenmask[wl];
+  const uint32_t a0 = __builtin_amdgcn_alignbyte(d1, d0, sh) & m.x;
+  const uint32_t a1 = __builtin_amdgcn_alignbyte(d2, d1, sh) & m.y;
+  const uint32_t a2 = __builtin_amdgcn_alignbyte(d3, d2, sh) & m.z;
+  const uint32_t a3 = __builtin_amdgcn_alignbyte(d4, d3, sh) & m.w;
+  *lo = (uint64_t)a0 | ((uint64_t)a1 << 32);
+  *hi = (uint64_t)a2 | ((uint64_t)a3 << 32);
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave: shifts within each 16-lane row, then the
 // row broadcasts of lanes 15 and 31 (lanes whose source is outside the row, and rows the mask
 // leaves out, add 0).
