@@ -58,16 +58,6 @@ WC_DEV uint64_t short_key_g(uint64_t lo, uint64_t hi, uint64_t key_mask) {
   return finish_key(fnv_packed(lo, hi, packed_len(lo, hi)), key_mask);
 }
 
-// Index of the word in the dictionary, or -1: the displacement of its group, the key index in
-// its slot, one key compare (an empty slot points at the all-zero key).
-WC_DEV int dict_find(const uint16_t* disp, const uint16_t* slots, const uint4* keys, uint64_t lo,
-                     uint64_t hi, uint32_t h) {
-  const uint32_t i = slots[dict_slot(h, disp[dict_group(h)])];
-  const uint4 k = keys[i];
-  const uint4 want = key4(lo, hi);
-  return (k.x == want.x && k.y == want.y && k.z == want.z && k.w == want.w) ? (int)i : -1;
-}
-
 // ---------------------------------------------------------------------------------------
 // LDS table of short words (lo, hi, count); no deletions while counting
 // ---------------------------------------------------------------------------------------
@@ -544,7 +534,8 @@ constexpr int kMapWaves = kMapBlock / 64;
 
 size_t global_map_dyn(uint32_t dict_cap) {
   return (size_t)kMapWaves * kStripeText +
-         (size_t)(kDispBuckets + kDictSlots) * 2 + (size_t)(dict_cap + 1) * 16 + (size_t)dict_cap * 4 +
+         (size_t)kDispBuckets * 4 + (size_t)kDictSlots * 2 + (size_t)(dict_cap + 1) * 16 +
+         (size_t)dict_cap * 4 +
          (size_t)kMapWaves * kWaveStarts * 4;
 }
 
@@ -583,8 +574,11 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
 
   const uint32_t D = P.dict_cap;
   uint8_t* s_txt = s_dyn;                                       // [NW][kStripeText]
-  uint16_t* s_disp = (uint16_t*)(s_txt + NW * kStripeText);    // [kDispBuckets]
-  uint16_t* s_dslot = s_disp + kDispBuckets;                    // [kDictSlots]
+  // group g's displacement d (8 bits and the field select) unpacked for the lookup: the byte
+  // offset of its slot region in s_dslot (bits 16..31), the field's shift (bits 8..12), d's low
+  // 8 bits (bits 0..7)
+  uint32_t* s_disp = (uint32_t*)(s_txt + NW * kStripeText);    // [kDispBuckets]
+  uint16_t* s_dslot = (uint16_t*)(s_disp + kDispBuckets);       // [kDictSlots]
   uint4* s_keys = (uint4*)(s_dslot + kDictSlots);               // [D + 1]
   uint32_t* s_cnt = (uint32_t*)(s_keys + D + 1);                // [D]
   uint32_t* s_pairs = s_cnt + D;                                // [NW][kWaveStarts]
@@ -599,7 +593,11 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   const int64_t R0 = (int64_t)P.offsets[0], R1 = (int64_t)P.offsets[P.n_docs];
 
   const uint32_t nd = P.dict->n;
-  for (uint32_t i = tid; i < kDispBuckets; i += BLOCK) s_disp[i] = P.dict->disp[i];
+  for (uint32_t i = tid; i < kDispBuckets; i += BLOCK) {
+    const uint32_t d = P.dict->disp[i];
+    s_disp[i] = ((i & (kDictRegions - 1)) << 25) |
+                ((__builtin_ctz(kDispBuckets) + 8 * ((d >> 8) & 1u)) << 8) | (d & 0xffu);
+  }
   for (uint32_t i = tid; i < kDictSlots; i += BLOCK) s_dslot[i] = P.dict->slot[i];
   for (uint32_t i = tid; i <= nd; i += BLOCK) s_keys[i] = P.dict->keys[i];
   for (uint32_t i = tid; i < nd; i += BLOCK) s_cnt[i] = 0;
@@ -686,12 +684,16 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
       pack_word_lm(my_txt, s2[x], s_lenmask, f2[x] ? n2[x] : 1u, &lo2[x], &hi2[x]);
       h2[x] = word_hash32(lo2[x], hi2[x]);
     }
+    // the perfect hash's slot (dict_slot) from the unpacked displacement
     uint32_t d2[2], i2[2];
     uint4 k2[2];
 #pragma unroll
     for (int x = 0; x < 2; ++x) d2[x] = s_disp[dict_group(h2[x])];
 #pragma unroll
-    for (int x = 0; x < 2; ++x) i2[x] = s_dslot[dict_slot(h2[x], d2[x])];
+    for (int x = 0; x < 2; ++x) {
+      const uint32_t f = (h2[x] >> ((d2[x] >> 8) & 31u)) ^ d2[x];
+      i2[x] = *(const uint16_t*)((const uint8_t*)s_dslot + (d2[x] >> 16) + ((f & 0xffu) << 1));
+    }
 #pragma unroll
     for (int x = 0; x < 2; ++x) k2[x] = s_keys[i2[x]];
     bool m2[2];
@@ -735,8 +737,11 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
   auto stripe_pos = [&](uint64_t i) -> int64_t {
     return P.base_off + (int64_t)((sw0 + i) * kStripe);
   };
+  // a stripe inside the text (the wave-uniform common case) is loaded without per-lane checks
   auto load_main = [&](uint64_t i) -> uint4 {
-    return load_text16(P.corpus, P.len, stripe_pos(i) + lane * 16);
+    const int64_t p = stripe_pos(i);
+    if (p >= 0 && p + (int64_t)kStripe <= (int64_t)P.len) return load_stream16(P.corpus + p + lane * 16);
+    return load_text16(P.corpus, P.len, p + lane * 16);
   };
 
   const uint4 blank = make_uint4(0x20202020u, 0x20202020u, 0x20202020u, 0x20202020u);

@@ -40,7 +40,7 @@ constexpr uint32_t kMapBlock = 1024;     // pass-1 workgroup
 constexpr uint32_t kGlobalStage = kMapBlock * 16;  // bytes scanned per pass-1 stage
 constexpr uint32_t kDispBuckets = 1024;   // dictionary: displacement buckets (low 9 hash bits)
 constexpr uint32_t kDictSlots = 8192;    // dictionary: slots of the perfect hash
-constexpr uint32_t kDictRegions = 32;    // dictionary: regions of 256 slots (group mod 16)
+constexpr uint32_t kDictRegions = 32;    // dictionary: regions of 256 slots (group mod 32)
 constexpr uint32_t kSampleStages = 512;  // pass-1 stages sampled (first 8 KiB of each)
 constexpr uint32_t kSamplePer = 2;       // sampled stages per sample workgroup
 constexpr uint32_t kSampleLds = 2048;    // LDS table of one sample workgroup
