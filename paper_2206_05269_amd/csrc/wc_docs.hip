@@ -319,35 +319,47 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
         }
         // short words: packed, keyed and looked up together (the common case: the key has an
         // entry in its home group); the rest through the general insert, one at a time
+        // (each LDS step reads for both tokens before either waits: pin)
+        PackSrc ps[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) ps[x] = pack_read(my_txt, s2[x]);
+#pragma unroll
+        for (int x = 0; x < 2; ++x) pin(ps[x]);
         uint64_t lo2[2], hi2[2];
         uint4 key2[2];
         uint32_t h2[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
-          pack_word(my_txt, s2[x], sh2[x] ? wl2[x] : 1u, &lo2[x], &hi2[x]);
+          pack_join(ps[x], sh2[x] ? wl2[x] : 1u, &lo2[x], &hi2[x]);
           key2[x] = key4(lo2[x], recount ? hi2[x] : hi_with_doc(hi2[x], r2[x]));
           h2[x] = red_hash(key2[x]);
         }
         uint4 g2[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) g2[x] = ((const uint4*)T.slot)[red_group(h2[x])];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) pin(g2[x]);
         uint32_t e2[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
+          // the first slot whose tag matches (selected from the last slot back, no branches)
           const uint32_t tag = red_tag(h2[x]);
-          e2[x] = (g2[x].x >> 13) == tag   ? g2[x].x
-                  : (g2[x].y >> 13) == tag ? g2[x].y
-                  : (g2[x].z >> 13) == tag ? g2[x].z
-                  : (g2[x].w >> 13) == tag ? g2[x].w
-                                           : 0u;
+          uint32_t m = 0u;
+          m = (g2[x].w >> 13) == tag ? g2[x].w : m;
+          m = (g2[x].z >> 13) == tag ? g2[x].z : m;
+          m = (g2[x].y >> 13) == tag ? g2[x].y : m;
+          m = (g2[x].x >> 13) == tag ? g2[x].x : m;
+          e2[x] = m;
         }
         uint4 k2[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) k2[x] = T.key[e2[x] & 0x1fffu];
 #pragma unroll
+        for (int x = 0; x < 2; ++x) pin(k2[x]);
+#pragma unroll
         for (int x = 0; x < 2; ++x) {
-          const bool hit = sh2[x] && e2[x] && k2[x].x == key2[x].x && k2[x].y == key2[x].y &&
-                           k2[x].z == key2[x].z && k2[x].w == key2[x].w;
+          const bool eq = key_eq(k2[x], key2[x]);
+          const bool hit = sh2[x] & (e2[x] != 0) & eq;
           if (hit) atomicAdd(&T.cnt[e2[x] & 0x1fffu], 1u);
           sh2[x] = sh2[x] && !hit;
         }

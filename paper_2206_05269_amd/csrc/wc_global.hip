@@ -327,36 +327,58 @@ __global__ void dict_hist_kernel(GlobalParams P) {
     if (h[i]) atomicAdd(&P.dict->hist[i], h[i]);
 }
 
-__global__ void dict_select_kernel(GlobalParams P) {
-  __shared__ uint32_t s_t, s_acc, s_room;
+// The selected words of a workgroup's slots are listed in LDS and take their places in the
+// dictionary with one device atomic per list (a word that finds the list full takes its own).
+__global__ __launch_bounds__(256) void dict_select_kernel(GlobalParams P) {
+  constexpr uint32_t kList = 256;
+  __shared__ uint32_t s_t, s_acc, s_room, s_n[2], s_base[2];
+  __shared__ uint4 s_key[2][kList];
+  __shared__ uint32_t s_c[2][kList];
   if (threadIdx.x == 0) {
     uint32_t t, acc, room;
     dict_threshold(P.dict->hist, P.dict_cap, &t, &acc, &room);
     s_t = t;
     s_acc = acc;
     s_room = room;
+    s_n[0] = s_n[1] = 0;
   }
   __syncthreads();
   const uint32_t t = s_t, acc = s_acc, room = s_room;
+  // list 0: count >= t (all fit, positions from 0); list 1: count t - 1 (the first `room` of
+  // them fit, positions from acc)
+  auto place = [&](uint32_t which, uint32_t j, const uint4 k, uint32_t c) {
+    if (which == 0 ? j < acc : j < room) {
+      P.dict->keys[(which == 0 ? 0u : acc) + j] = k;
+      P.dict->cnt[(which == 0 ? 0u : acc) + j] = c;
+    }
+  };
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kSampleSlots;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const Slot s = P.sample_table[i];
     if (!s.key) continue;
     const uint32_t c = s.cnt < 255 ? (uint32_t)s.cnt : 255u;
+    const uint32_t which = c >= t ? 0u : (c + 1 == t && room) ? 1u : 2u;
+    if (which == 2) continue;
     const uint4 k = key4(s.w0, s.w1 & ~kTop);
-    if (c >= t) {
-      uint32_t j = atomicAdd(&P.dict->n_high, 1u);
-      if (j < acc) {
-        P.dict->keys[j] = k;
-        P.dict->cnt[j] = c;
-      }
-    } else if (c + 1 == t && room) {
-      uint32_t j = atomicAdd(&P.dict->n_low, 1u);
-      if (j < room) {
-        P.dict->keys[acc + j] = k;
-        P.dict->cnt[acc + j] = c;
-      }
+    const uint32_t l = atomicAdd(&s_n[which], 1u);
+    if (l < kList) {
+      s_key[which][l] = k;
+      s_c[which][l] = c;
+    } else {
+      place(which, atomicAdd(which == 0 ? &P.dict->n_high : &P.dict->n_low, 1u), k, c);
     }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const uint32_t n = min(s_n[threadIdx.x], kList);
+    s_base[threadIdx.x] =
+        n ? atomicAdd(threadIdx.x == 0 ? &P.dict->n_high : &P.dict->n_low, n) : 0u;
+  }
+  __syncthreads();
+  for (uint32_t which = 0; which < 2; ++which) {
+    const uint32_t n = min(s_n[which], kList);
+    for (uint32_t l = threadIdx.x; l < n; l += blockDim.x)
+      place(which, s_base[which] + l, s_key[which][l], s_c[which][l]);
   }
 }
 
@@ -677,11 +699,24 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     for (int x = 0; x < 2; ++x)
       if (lane + 64 * x < nw && !f2[x])
         long_token(p0, s2[x], n2[x] ? s2[x] + n2[x] - 1 : kLongEnd);
+    // each LDS step reads for both tokens before either waits (pin)
+    PackSrc ps[2];
+    uint4 lm[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      ps[x] = pack_read(my_txt, s2[x]);
+      lm[x] = s_lenmask[f2[x] ? n2[x] : 1u];
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      pin(ps[x]);
+      pin(lm[x]);
+    }
     uint64_t lo2[2], hi2[2];
     uint32_t h2[2];
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
-      pack_word_lm(my_txt, s2[x], s_lenmask, f2[x] ? n2[x] : 1u, &lo2[x], &hi2[x]);
+      pack_join(ps[x], lm[x], &lo2[x], &hi2[x]);
       h2[x] = word_hash32(lo2[x], hi2[x]);
     }
     // the perfect hash's slot (dict_slot) from the unpacked displacement
@@ -690,18 +725,22 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
 #pragma unroll
     for (int x = 0; x < 2; ++x) d2[x] = s_disp[dict_group(h2[x])];
 #pragma unroll
+    for (int x = 0; x < 2; ++x) pin(d2[x]);
+#pragma unroll
     for (int x = 0; x < 2; ++x) {
       const uint32_t f = (h2[x] >> ((d2[x] >> 8) & 31u)) ^ d2[x];
       i2[x] = *(const uint16_t*)((const uint8_t*)s_dslot + (d2[x] >> 16) + ((f & 0xffu) << 1));
     }
 #pragma unroll
+    for (int x = 0; x < 2; ++x) pin(i2[x]);
+#pragma unroll
     for (int x = 0; x < 2; ++x) k2[x] = s_keys[i2[x]];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) pin(k2[x]);
     bool m2[2];
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
-      const uint4 want = key4(lo2[x], hi2[x]);
-      const bool hit = k2[x].x == want.x && k2[x].y == want.y && k2[x].z == want.z &&
-                       k2[x].w == want.w;
+      const bool hit = key_eq(k2[x], key4(lo2[x], hi2[x]));
       if (f2[x] && hit) atomicAdd(&s_cnt[i2[x]], 1u);
       m2[x] = f2[x] && !hit;
     }
@@ -947,14 +986,44 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   static_assert(kBlockRec % 64 == 0, "a block spans whole waves");
   // kRec records per lane at once: the common case for all of them, then the rest one at a time
   constexpr int kRec = 4;
+  // The common case (a word with an entry, found by the first tag match of its home group) is
+  // taken for all kRec records together: every slot group is read, then every candidate key,
+  // so a wave waits for two LDS round trips per kRec records instead of several per record.
   auto add_records = [&](const uint4* v, const bool* use) {
-    uint32_t h[kRec];
+    uint32_t h[kRec], e[kRec];
+    uint4 s4[kRec], k4[kRec];
     bool d[kRec];
 #pragma unroll
-    for (int x = 0; x < kRec; ++x)
-      h[x] = red_hash(v[x]);
+    for (int x = 0; x < kRec; ++x) h[x] = red_hash(v[x]);
 #pragma unroll
-    for (int x = 0; x < kRec; ++x) d[x] = use[x] && !red_hit(T, v[x], h[x]);
+    for (int x = 0; x < kRec; ++x) s4[x] = ((const uint4*)T.slot)[red_group(h[x])];
+    // (pinned, each read stays whole: the optimiser would otherwise read the later slots of a
+    // group only when the earlier ones miss, one round trip after another)
+#pragma unroll
+    for (int x = 0; x < kRec; ++x) pin(s4[x]);
+#pragma unroll
+    for (int x = 0; x < kRec; ++x) {
+      // the first slot whose tag matches (selects from the last slot back, without branches)
+      const uint32_t tag = red_tag(h[x]);
+      uint32_t m = 0u;
+      m = (s4[x].w >> 13) == tag ? s4[x].w : m;
+      m = (s4[x].z >> 13) == tag ? s4[x].z : m;
+      m = (s4[x].y >> 13) == tag ? s4[x].y : m;
+      m = (s4[x].x >> 13) == tag ? s4[x].x : m;
+      e[x] = m;
+    }
+    // (e = 0: entry 0 is read and not counted)
+#pragma unroll
+    for (int x = 0; x < kRec; ++x) k4[x] = T.key[e[x] & 0x1fffu];
+#pragma unroll
+    for (int x = 0; x < kRec; ++x) pin(k4[x]);
+#pragma unroll
+    for (int x = 0; x < kRec; ++x) {
+      const bool eq = key_eq(k4[x], v[x]);
+      const bool hit = use[x] & (e[x] != 0) & eq;
+      if (hit) atomicAdd(&T.cnt[e[x] & 0x1fffu], 1u);
+      d[x] = use[x] && !hit;
+    }
 #pragma unroll
     for (int x = 0; x < kRec; ++x) {
       if (__any(d[x])) {

@@ -52,16 +52,52 @@ WC_DEV uint32_t cut16(uint32_t w16, int64_t p, int64_t a, int64_t b) {
   return w16 & m;
 }
 
-// Packed bytes of the word at byte s of the staged text (1 <= wl <= 16 bytes, all staged):
-// five dword reads, byte alignment, and the bytes past the word cleared.
-WC_DEV void pack_word(const uint8_t* s_txt, uint32_t s, uint32_t wl, uint64_t* lo, uint64_t* hi) {
+// Keeps a value in VGPRs at this point of the program: every load that produces it is issued
+// before it, and the optimiser can neither split a wide LDS read into parts read one after
+// another nor move the read into a branch. Pinning the results of several independent reads
+// together makes a wave wait once for all of them.
+WC_DEV void pin(uint32_t& v) { __asm__ volatile("" : "+v"(v)); }
+WC_DEV void pin(uint4& v) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // one register quad
+  u32x4 t = {v.x, v.y, v.z, v.w};
+  __asm__ volatile("" : "+v"(t));
+  v = make_uint4(t.x, t.y, t.z, t.w);
+}
+
+// a == b for two 16-byte keys, as one OR of XORs (pinned, so that it is not turned back into
+// four compares and branches)
+WC_DEV bool key_eq(const uint4 a, const uint4 b) {
+  uint32_t d = (a.x ^ b.x) | (a.y ^ b.y) | (a.z ^ b.z) | (a.w ^ b.w);
+  pin(d);
+  return d == 0;
+}
+
+// Packing a word of the staged text in two steps, so that the LDS reads of several words can
+// be issued together: pack_read takes the five dwords that hold the 16 bytes from byte s,
+// pack_join aligns them and clears the bytes past the word (1 <= wl <= 16, all staged).
+struct PackSrc {
+  uint32_t d[5];
+  uint32_t sh;
+};
+WC_DEV PackSrc pack_read(const uint8_t* s_txt, uint32_t s) {
   const uint32_t* tw = (const uint32_t*)s_txt;
-  const uint32_t di = s >> 2, sh = s & 3;
-  const uint32_t d0 = tw[di], d1 = tw[di + 1], d2 = tw[di + 2], d3 = tw[di + 3], d4 = tw[di + 4];
-  uint64_t a = (uint64_t)__builtin_amdgcn_alignbyte(d1, d0, sh) |
-               ((uint64_t)__builtin_amdgcn_alignbyte(d2, d1, sh) << 32);
-  uint64_t b = (uint64_t)__builtin_amdgcn_alignbyte(d3, d2, sh) |
-               ((uint64_t)__builtin_amdgcn_alignbyte(d4, d3, sh) << 32);
+  const uint32_t di = s >> 2;
+  PackSrc r;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) r.d[j] = tw[di + j];
+  r.sh = s & 3;
+  return r;
+}
+WC_DEV void pin(PackSrc& r) {
+#pragma unroll
+  for (int j = 0; j < 5; ++j) pin(r.d[j]);
+}
+// the bytes past the word cleared with computed shifts
+WC_DEV void pack_join(const PackSrc& r, uint32_t wl, uint64_t* lo, uint64_t* hi) {
+  uint64_t a = (uint64_t)__builtin_amdgcn_alignbyte(r.d[1], r.d[0], r.sh) |
+               ((uint64_t)__builtin_amdgcn_alignbyte(r.d[2], r.d[1], r.sh) << 32);
+  uint64_t b = (uint64_t)__builtin_amdgcn_alignbyte(r.d[3], r.d[2], r.sh) |
+               ((uint64_t)__builtin_amdgcn_alignbyte(r.d[4], r.d[3], r.sh) << 32);
   const uint32_t ka = wl < 8 ? 64 - 8 * wl : 0u;    // bits of a past the word
   const uint32_t kb = wl < 16 ? 128 - 8 * wl : 0u;  // bits of b past the word (>= 64: all)
   a = (a << ka) >> ka;
@@ -69,8 +105,22 @@ WC_DEV void pack_word(const uint8_t* s_txt, uint32_t s, uint32_t wl, uint64_t* l
   *lo = a;
   *hi = b;
 }
+// the bytes past the word cleared with m, the word length's entry of the init_len_masks table
+WC_DEV void pack_join(const PackSrc& r, const uint4 m, uint64_t* lo, uint64_t* hi) {
+  const uint32_t a0 = __builtin_amdgcn_alignbyte(r.d[1], r.d[0], r.sh) & m.x;
+  const uint32_t a1 = __builtin_amdgcn_alignbyte(r.d[2], r.d[1], r.sh) & m.y;
+  const uint32_t a2 = __builtin_amdgcn_alignbyte(r.d[3], r.d[2], r.sh) & m.z;
+  const uint32_t a3 = __builtin_amdgcn_alignbyte(r.d[4], r.d[3], r.sh) & m.w;
+  *lo = (uint64_t)a0 | ((uint64_t)a1 << 32);
+  *hi = (uint64_t)a2 | ((uint64_t)a3 << 32);
+}
 
-// Byte masks of the first n of 16 bytes, n = 0..16 (one uint4 each), for pack_word_lm.
+// Packed bytes of the word at byte s of the staged text (1 <= wl <= 16 bytes, all staged).
+WC_DEV void pack_word(const uint8_t* s_txt, uint32_t s, uint32_t wl, uint64_t* lo, uint64_t* hi) {
+  pack_join(pack_read(s_txt, s), wl, lo, hi);
+}
+
+// Byte masks of the first n of 16 bytes, n = 0..16 (one uint4 each), for pack_join.
 WC_DEV void init_len_masks(uint4* m, uint32_t tid, uint32_t nthreads) {
   for (uint32_t n = tid; n <= 16; n += nthreads) {
     uint32_t w[4];
@@ -81,22 +131,6 @@ WC_DEV void init_len_masks(uint4* m, uint32_t tid, uint32_t nthreads) {
     }
     m[n] = make_uint4(w[0], w[1], w[2], w[3]);
   }
-}
-
-// pack_word with the bytes past the word cleared by a mask read from the table of
-// init_len_masks (issued beside the text reads) instead of computed shifts.
-WC_DEV void pack_word_lm(const uint8_t* s_txt, uint32_t s, const uint4* lenmask, uint32_t wl,
-                         uint64_t* lo, uint64_t* hi) {
-  const uint32_t* tw = (const uint32_t*)s_txt;
-  const uint32_t di = s >> 2, sh = s & 3;
-  const uint32_t d0 = tw[di], d1 = tw[di + 1], d2 = tw[di + 2], d3 = tw[di + 3], d4 = tw[di + 4];
-  const uint4 m = lenmask[wl];
-  const uint32_t a0 = __builtin_amdgcn_alignbyte(d1, d0, sh) & m.x;
-  const uint32_t a1 = __builtin_amdgcn_alignbyte(d2, d1, sh) & m.y;
-  const uint32_t a2 = __builtin_amdgcn_alignbyte(d3, d2, sh) & m.z;
-  const uint32_t a3 = __builtin_amdgcn_alignbyte(d4, d3, sh) & m.w;
-  *lo = (uint64_t)a0 | ((uint64_t)a1 << 32);
-  *hi = (uint64_t)a2 | ((uint64_t)a3 << 32);
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave: shifts within each 16-lane row, then the
