@@ -986,32 +986,30 @@ __global__ __launch_bounds__(BLOCK) void global_reduce_kernel(GlobalParams P) {
   static_assert(kBlockRec % 64 == 0, "a block spans whole waves");
   // kRec records per lane at once: the common case for all of them, then the rest one at a time
   constexpr int kRec = 4;
-  // The common case (a word with an entry, found by the first tag match of its home group) is
-  // taken for all kRec records together: every slot group is read, then every candidate key,
-  // so a wave waits for two LDS round trips per kRec records instead of several per record.
+  // The common case (a word with an entry, found by the first tag match in the first two groups
+  // of its probe sequence) is taken for all kRec records together: every pair of slot groups is
+  // read, then every candidate key, so a wave waits for two LDS round trips per kRec records
+  // instead of several per record.
   auto add_records = [&](const uint4* v, const bool* use) {
     uint32_t h[kRec], e[kRec];
-    uint4 s4[kRec], k4[kRec];
+    uint4 sa[kRec], sb[kRec], k4[kRec];
     bool d[kRec];
 #pragma unroll
     for (int x = 0; x < kRec; ++x) h[x] = red_hash(v[x]);
 #pragma unroll
-    for (int x = 0; x < kRec; ++x) s4[x] = ((const uint4*)T.slot)[red_group(h[x])];
+    for (int x = 0; x < kRec; ++x) {
+      sa[x] = ((const uint4*)T.slot)[red_group(h[x])];
+      sb[x] = ((const uint4*)T.slot)[red_next_group(red_group(h[x]))];
+    }
     // (pinned, each read stays whole: the optimiser would otherwise read the later slots of a
     // group only when the earlier ones miss, one round trip after another)
 #pragma unroll
-    for (int x = 0; x < kRec; ++x) pin(s4[x]);
-#pragma unroll
     for (int x = 0; x < kRec; ++x) {
-      // the first slot whose tag matches (selects from the last slot back, without branches)
-      const uint32_t tag = red_tag(h[x]);
-      uint32_t m = 0u;
-      m = (s4[x].w >> 13) == tag ? s4[x].w : m;
-      m = (s4[x].z >> 13) == tag ? s4[x].z : m;
-      m = (s4[x].y >> 13) == tag ? s4[x].y : m;
-      m = (s4[x].x >> 13) == tag ? s4[x].x : m;
-      e[x] = m;
+      pin(sa[x]);
+      pin(sb[x]);
     }
+#pragma unroll
+    for (int x = 0; x < kRec; ++x) e[x] = red_pick8(sa[x], sb[x], red_tag(h[x]));
     // (e = 0: entry 0 is read and not counted)
 #pragma unroll
     for (int x = 0; x < kRec; ++x) k4[x] = T.key[e[x] & 0x1fffu];

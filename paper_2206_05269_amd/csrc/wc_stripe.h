@@ -215,6 +215,27 @@ WC_DEV uint32_t red_hash(const uint4 v) {
 WC_DEV uint32_t red_tag(uint32_t h) { return ((h >> 2) & 0x7ffffu) | 1u; }
 WC_DEV uint32_t red_group(uint32_t h) { return h >> 21; }
 
+// The fast path of a lookup reads the first two groups of a key's probe sequence, its home
+// group and the next: a key moves on to the next group only when its home group is full, so a
+// key with an entry sits in one of them unless both were full when it was added. (With the
+// home group alone, the keys of full groups, a few percent, missed the fast path on every
+// occurrence, and a wave took the general insert whenever one of its lanes held such a key.)
+WC_DEV uint32_t red_next_group(uint32_t g) { return (g + 1) & (kRedSlots / 4 - 1); }
+// the first of the eight slots of groups a, b (in probe order) whose tag matches, or 0;
+// selected from the last slot back, without branches
+WC_DEV uint32_t red_pick8(const uint4 a, const uint4 b, uint32_t tag) {
+  uint32_t m = 0u;
+  m = (b.w >> 13) == tag ? b.w : m;
+  m = (b.z >> 13) == tag ? b.z : m;
+  m = (b.y >> 13) == tag ? b.y : m;
+  m = (b.x >> 13) == tag ? b.x : m;
+  m = (a.w >> 13) == tag ? a.w : m;
+  m = (a.z >> 13) == tag ? a.z : m;
+  m = (a.y >> 13) == tag ? a.y : m;
+  m = (a.x >> 13) == tag ? a.x : m;
+  return m;
+}
+
 // The common case: the word has an entry, found by the first tag match of its home group.
 // Counts it and returns true; false sends the word to red_add.
 WC_DEV bool red_hit(const RedTable& T, const uint4 want, uint32_t h) {
