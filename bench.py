@@ -571,7 +571,7 @@ def batched_docs_per_s(steps: int, warmup: int, plain_docs: int):
                      use_cache=False)
     t_tune = time.perf_counter() - t0
     log(f"autotune: chunk {tu.chunk_bytes} lds {tu.lds_entries} load {tu.lds_load_pct}% "
-        f"in {t_tune:.1f} s")
+        f"direct {tu.direct_kib} KiB in {t_tune:.1f} s")
     b = wc.Batch(max_docs=n_docs, max_bytes=B, count_bytes=4, tuning=tu,
                  **wc.output_sizes(c.text, c.offsets, count_bytes=4))
     for _ in range(warmup):
@@ -610,7 +610,8 @@ def batched_docs_per_s(steps: int, warmup: int, plain_docs: int):
            "plain_docs_per_s": round(1.0 / dt_p, 1), "plain_sample_docs": m,
            "speedup": round((n_docs / dt_b) * dt_p, 1),
            "tuning": {"chunk_bytes": tu.chunk_bytes, "lds_entries": tu.lds_entries,
-                      "lds_load_pct": tu.lds_load_pct, "calibration_docs": cal,
+                      "lds_load_pct": tu.lds_load_pct, "direct_kib": tu.direct_kib,
+                      "calibration_docs": cal,
                       "tune_s": round(t_tune, 1)}}
     log(f"batched {res['batched_docs_per_s']} docs/s vs plain {res['plain_docs_per_s']} docs/s")
     return res

@@ -93,7 +93,14 @@ typedef struct wc_tuning {
                              it is then counted again with a private table); 0 = default */
   uint32_t chunk_bytes;   /* per-document mode: bytes per work item, power of two in
                              16 KiB..1 MiB (0 = 64 KiB) */
+  uint32_t direct_kib;    /* per-document mode, document-centric kernel: a document longer
+                             than chunk_bytes and than this many KiB skips the first,
+                             optimistic count (in which it would likely overflow the LDS
+                             table) and is counted once, by the second pass (0 = twice
+                             chunk_bytes; WC_DIRECT_NEVER = no document skips it) */
 } wc_tuning;
+
+#define WC_DIRECT_NEVER 0xffffffffu
 
 typedef struct wc_opts {
   uint32_t count_bytes;      /* width of exported counts: 4 (int32) or 8 (int64) */

@@ -55,6 +55,7 @@ struct Bump {
 
 struct Tune {
   uint32_t block, stage, lds, policy, grid, flush_at, pct, chunk;
+  uint32_t direct_kib;  // document-centric kernel: 0 = no document skips the first count
 };
 
 int device_cus() {
@@ -85,6 +86,8 @@ bool resolve_tuning(const wc_tuning* t, Tune* out) {
   u.flush_at = (uint32_t)((uint64_t)u.lds * pct / 100);
   u.chunk = t && t->chunk_bytes ? t->chunk_bytes : (uint32_t)kWin;
   if (!is_pow2(u.chunk) || u.chunk < kMinWin || u.chunk > (1u << 20)) return false;
+  const uint32_t dk = t ? t->direct_kib : 0u;
+  u.direct_kib = dk == WC_DIRECT_NEVER ? 0u : dk ? dk : 2 * (u.chunk >> 10);
   *out = u;
   return true;
 }
@@ -200,12 +203,12 @@ void layout_docs(uint64_t len, uint64_t n_docs, const wc_opts* o, void* ws, DocL
 }
 
 DocParams doc_params(const DocLayout& L, const wc_opts* o, uint32_t lds, uint32_t pct,
-                     uint32_t chunk) {
+                     uint32_t chunk, uint32_t direct_kib) {
   DocParams P;
   P.lds_cap = (uint32_t)((uint64_t)lds * (pct ? pct : 75) / 100);
   if (P.lds_cap < 1) P.lds_cap = 1;
   if (P.lds_cap > lds - lds / 8) P.lds_cap = lds - lds / 8;
-  P.pad0 = 0;
+  P.direct_kib = direct_kib;
   P.win_bytes = chunk;
   P.task = L.task;
   P.hdr = L.hdr;
@@ -449,7 +452,7 @@ wc_status wc_count(const uint8_t* d_corpus, uint64_t corpus_len, const uint64_t*
     HIPCHK(hipMemcpyAsync(D.task, &task, sizeof(task), hipMemcpyHostToDevice, s));
     HIPCHK(launch_fill_zero(D.hdr, sizeof(Header), s));
     uint32_t grid = tu.grid ? tu.grid : (uint32_t)device_cus();
-    DocParams P = doc_params(D, opts, lds, tu.pct, tu.chunk);
+    DocParams P = doc_params(D, opts, lds, tu.pct, tu.chunk, tu.direct_kib);
     if (tm.on) HIPCHK(hipEventRecord(tm.a, s));
     HIPCHK(launch_docs(P, grid, doc_dyn(lds), s));
     if (tm.on) HIPCHK(hipEventRecord(tm.b, s));
@@ -1068,7 +1071,7 @@ wc_status wc_batch_run(wc_batch* b, const uint8_t* d_corpus, uint64_t corpus_len
     HIPCHK(hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal));
     Tune tu;
     resolve_tuning(b->opts.tuning, &tu);
-    DocParams P = doc_params(b->D, &b->opts, b->lds, tu.pct, tu.chunk);
+    DocParams P = doc_params(b->D, &b->opts, b->lds, tu.pct, tu.chunk, tu.direct_kib);
     hipError_t e = hipMemcpyAsync(b->D.task, b->h_task, sizeof(DocTask), hipMemcpyHostToDevice,
                                   b->bs);
     if (e == hipSuccess) e = launch_fill_zero(b->D.hdr, sizeof(Header), b->bs);
@@ -1132,14 +1135,14 @@ std::vector<wc_tuning> tune_grid(const wc_opts* o) {
   if (o->mode == WC_PER_DOC) {
     for (uint32_t chunk : {32u << 10, 64u << 10, 128u << 10})
       for (uint32_t lds : {2048u, 4096u})
-        for (uint32_t pct : {60u, 85u}) g.push_back(wc_tuning{0, lds, 0, 0, pct, chunk});
+        for (uint32_t pct : {60u, 85u}) g.push_back(wc_tuning{0, lds, 0, 0, pct, chunk, 0});
   } else {
     // one-pass kernel: LDS entries x flush load x flush policy (the two-pass kernels, from
     // 256 MiB, take lds_entries as the dictionary size and ignore the rest)
     for (uint32_t lds : {2048u, 4096u})
       for (uint32_t pct : {60u, 75u, 90u})
         for (uint32_t pol : {WC_FLUSH_ALL, WC_FLUSH_BYPASS})
-          g.push_back(wc_tuning{0, lds, pol, 0, pct, 0});
+          g.push_back(wc_tuning{0, lds, pol, 0, pct, 0, 0});
   }
   return g;
 }
@@ -1171,7 +1174,12 @@ wc_status wc_autotune(const uint8_t* d_sample, uint64_t len, const uint64_t* d_o
   if (!best || !opts_ok(opts)) return WC_EINVAL;
   float best_t = 3.4e38f;
   bool found = false;
-  for (const wc_tuning& t : tune_grid(opts)) {
+  // times one point (two calls after a warm-up); false when it needs more room than planned.
+  // (direct_kib keeps its default: on a calibration sample of a few thousand documents the
+  // second pass's time is that of its largest document, whatever the size limit, and the
+  // sample favoured sending every long document straight to it, which was slower on the
+  // whole corpus.)
+  auto try_point = [&](const wc_tuning& t, wc_status* err) -> bool {
     wc_opts o = *opts;
     o.tuning = &t;
     o.debug_flags |= WC_DEBUG_TIME;
@@ -1184,13 +1192,19 @@ wc_status wc_autotune(const uint8_t* d_sample, uint64_t len, const uint64_t* d_o
                     stream);
       if (rep) ms += r.total_ms;
     }
-    if (st == WC_EDEVICE) return st;
-    if (st != WC_OK) continue;  // a point that needs more room than planned is skipped
+    if (st == WC_EDEVICE) *err = st;
+    if (st != WC_OK) return false;  // a point that needs more room than planned is skipped
     if (ms < best_t) {
       best_t = ms;
       *best = t;
       found = true;
     }
+    return true;
+  };
+  wc_status err = WC_OK;
+  for (const wc_tuning& t : tune_grid(opts)) {
+    try_point(t, &err);
+    if (err != WC_OK) return err;
   }
   if (!found) return WC_ENOMEM;
   if (best_ms) *best_ms = best_t / 2;

@@ -100,6 +100,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   __shared__ uint64_t s_item, s_e0, s_b0, s_pbase;
   __shared__ uint32_t s_pslots;
   __shared__ unsigned long long s_tokens;
+  __shared__ uint32_t s_direct;  // second pass: the document was queued without a first count
   static_assert(kWaveStarts / 2 + kEndWords <= kWaveStarts, "starts and ends fit a wave's list");
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -385,7 +386,8 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       tokens += 1;
       if (lane == 0) long_word(stripe_pos(nsw) - 16 + (int64_t)def_s, doc_end(def_r), def_r);
     }
-    if (!recount && lane == 0 && tokens) atomicAdd(&s_tokens, (unsigned long long)tokens);
+    if ((!recount || s_direct) && lane == 0 && tokens)
+      atomicAdd(&s_tokens, (unsigned long long)tokens);
   };
 
   // ---- emission of the LDS entries of documents [0, nd) that did not overflow ------------
@@ -618,7 +620,16 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
           clear_table();
           queue_over(ns, d0);
         }
-        if (big) {
+        if (big && P.direct_kib &&
+            offsets[d0 + nd] - offsets[d0 + nd - 1] > ((uint64_t)P.direct_kib << 10)) {
+          // large enough to overflow the LDS table: straight to the second pass, which also
+          // counts its tokens
+          if (tid == 0) {
+            const uint64_t q = atomicAdd((unsigned long long*)&hdr->over_n, 1ull);
+            P.over_docs[q] = (d0 + nd - 1) | kDirectDoc;
+          }
+          __syncthreads();
+        } else if (big) {
           const uint64_t d = d0 + nd - 1;
           __syncthreads();
           if (tid == 0) {
@@ -644,7 +655,8 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       const uint64_t q = s_item;
       __syncthreads();
       if (q >= n_over) break;
-      const uint64_t d = P.over_docs[q];
+      const uint64_t d = P.over_docs[q] & ~kDirectDoc;
+      if (tid == 0) s_direct = (P.over_docs[q] & kDirectDoc) != 0;
       recount_doc((int64_t)offsets[d], (int64_t)offsets[d + 1], d);
     }
   }

@@ -126,7 +126,7 @@ struct DocParams {
   uint32_t count_bytes;
   uint32_t lds_entries;
   uint32_t lds_cap;        // live LDS entries before relief
-  uint32_t pad0;
+  uint32_t direct_kib;     // documents above this many KiB (0: none) skip the first pass
   uint64_t win_bytes;      // work item window
   uint64_t* docs;          // [cap_e]
   uint64_t* doc_ptr;       // [n_docs]
@@ -138,6 +138,7 @@ struct DocParams {
   uint64_t key_mask;
   uint64_t count_bias;     // added to every exported count (debug; 0 normally)
 };
+constexpr uint64_t kDirectDoc = 1ull << 63;  // over_docs entry: queued without a first count
 size_t doc_dyn(uint32_t entries);  // dynamic LDS of the document kernel
 hipError_t set_doc_smem(size_t dyn);
 hipError_t launch_docs(const DocParams& P, uint32_t grid, size_t dyn, hipStream_t s);

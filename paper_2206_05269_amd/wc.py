@@ -22,6 +22,7 @@ WC_OK, WC_EINVAL, WC_ENOMEM, WC_ETABLEFULL, WC_EOVERFLOW, WC_EDEVICE, WC_EAGAIN 
     0, -1, -2, -3, -4, -5, -6
 WC_GLOBAL, WC_PER_DOC = 0, 1
 WC_FLUSH_ALL, WC_FLUSH_BYPASS = 0, 1
+WC_DIRECT_NEVER = 0xFFFFFFFF  # wc_tuning.direct_kib: no document skips the first count
 WC_DEBUG_TIME, WC_DEBUG_NO_LDS, WC_DEBUG_DIRECT, WC_DEBUG_SPILL, WC_DEBUG_DOCS = 1, 2, 4, 8, 16
 WC_FOLD_SQRT, WC_FOLD_ALT_HARMONIC = 0, 1
 WC_TOKENIZE_ASCII, WC_TOKENIZE_UTF8 = 0, 1
@@ -39,7 +40,8 @@ class WcError(RuntimeError):
 class Tuning(ctypes.Structure):
     _fields_ = [("stage_bytes", ctypes.c_uint32), ("lds_entries", ctypes.c_uint32),
                 ("flush_policy", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
-                ("lds_load_pct", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32)]
+                ("lds_load_pct", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32),
+                ("direct_kib", ctypes.c_uint32)]
 
 
 class Opts(ctypes.Structure):
@@ -266,8 +268,9 @@ def _opts(count_bytes, per_doc, table_slots, tuning, debug_flags, debug_hash_bit
 
 
 def make_tuning(stage_bytes=0, lds_entries=0, flush_policy=WC_FLUSH_ALL, grid_blocks=0,
-                lds_load_pct=0, chunk_bytes=0) -> Tuning:
-    return Tuning(stage_bytes, lds_entries, flush_policy, grid_blocks, lds_load_pct, chunk_bytes)
+                lds_load_pct=0, chunk_bytes=0, direct_kib=0) -> Tuning:
+    return Tuning(stage_bytes, lds_entries, flush_policy, grid_blocks, lds_load_pct, chunk_bytes,
+                  direct_kib)
 
 
 def count_plan(corpus_len: int, n_docs: int, *, count_bytes=8, per_doc=False, table_slots=0,
@@ -783,7 +786,8 @@ def autotune(corpus: torch.Tensor, offsets: torch.Tensor, *, per_doc: bool = Tru
     _require_cuda(corpus, "corpus")
     props = torch.cuda.get_device_properties(corpus.device)
     size_class = int(corpus.numel()).bit_length()
-    key = f"{props.name}|{props.multi_processor_count}|{'doc' if per_doc else 'global'}|{size_class}"
+    key = (f"{props.name}|{props.multi_processor_count}|{'doc' if per_doc else 'global'}|"
+           f"{size_class}|direct")
     path = _cache_file(cache_path)
     cache = {}
     if use_cache and os.path.exists(path):
@@ -814,7 +818,8 @@ def autotune(corpus: torch.Tensor, offsets: torch.Tensor, *, per_doc: bool = Tru
         raise WcError(st, "wc_autotune")
     if use_cache:
         cache[key] = {"tuning": [best.stage_bytes, best.lds_entries, best.flush_policy,
-                                 best.grid_blocks, best.lds_load_pct, best.chunk_bytes],
+                                 best.grid_blocks, best.lds_load_pct, best.chunk_bytes,
+                                 best.direct_kib],
                       "ms": ms.value}
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -928,8 +928,8 @@ def test_autotune_choice_is_exact_and_cached(tmp_path):
     assert tu.lds_entries in (2048, 4096) and tu.chunk_bytes in (32 << 10, 64 << 10, 128 << 10)
     assert os.path.exists(cache)
     tu2 = wc.autotune(t, o, per_doc=True, cache_path=cache)
-    assert (tu2.lds_entries, tu2.chunk_bytes, tu2.lds_load_pct) == \
-        (tu.lds_entries, tu.chunk_bytes, tu.lds_load_pct)
+    assert (tu2.lds_entries, tu2.chunk_bytes, tu2.lds_load_pct, tu2.direct_kib) == \
+        (tu.lds_entries, tu.chunk_bytes, tu.lds_load_pct, tu.direct_kib)
     check(c.text.numpy(), c.offsets.numpy(), per_doc=True, tuning=tu)
     b = wc.Batch(max_docs=len(c.offsets), max_bytes=len(c.text), tuning=tu,
                  **wc.output_sizes(t, o))
@@ -938,6 +938,31 @@ def test_autotune_choice_is_exact_and_cached(tmp_path):
     b.close()
     g = wc.autotune(t, o, per_doc=False, cache_path=cache)
     check(c.text.numpy(), c.offsets.numpy(), tuning=g, debug_flags=wc.WC_DEBUG_SPILL)
+
+
+@pytest.mark.parametrize("direct_kib", [1, 32, wc.WC_DIRECT_NEVER])
+def test_per_doc_direct_second_pass(direct_kib):
+    """Documents longer than a 16 KiB work item and than direct_kib KiB skip the first count:
+    counted once by the second pass (tokens included), the tables must not change."""
+    c = synth.generate("batched-100k", scale=0.002)
+    text, offs = c.text.numpy(), c.offsets.numpy()
+    tu = wc.make_tuning(chunk_bytes=16 << 10, lds_entries=4096, lds_load_pct=85,
+                        direct_kib=direct_kib)
+    check(text, offs, per_doc=True, tuning=tu, debug_flags=wc.WC_DEBUG_DOCS)
+    t, o = to_dev(text, offs)
+    got = wc.count(t, o, per_doc=True, count_bytes=4, tuning=tu, debug_flags=wc.WC_DEBUG_DOCS,
+                   **wc.output_sizes(t, o))
+    sizes = np.diff(offs)
+    if direct_kib != wc.WC_DIRECT_NEVER:
+        big = int(((sizes > (16 << 10)) & (sizes > (direct_kib << 10))).sum())
+        assert got.stats["docs_recounted"] >= big > 0
+    want = oracle.count(text, offs, per_doc=True)
+    b = wc.Batch(max_docs=len(offs), max_bytes=len(text), count_bytes=4, tuning=tu,
+                 **wc.output_sizes(t, o))
+    for _ in range(2):
+        r = b.run(t, o)
+        assert r.total_tokens == want.total and r.as_dict() == want.as_dict()
+    b.close()
 
 
 @pytest.mark.parametrize("chunk", [16 << 10, 32 << 10, 256 << 10, 1 << 20])
