@@ -155,8 +155,9 @@ typedef struct wc_result {
    * [4] records pass 2 could not sum in its LDS table (added to the global table).
    * Document-centric per-document count (the batch API, and wc_count in per-document mode for
    * small documents):
-   * [3] documents counted again in the kernel's second pass, with a private table in device
-   *     memory, because their words did not fit the LDS table. */
+   * [3] documents counted in the kernel's second pass, with a private table in device
+   *     memory: those whose words did not fit the LDS table, and those that skipped the
+   *     first pass by size (wc_tuning.direct_kib). */
   uint64_t stats[5];
 } wc_result;
 
