@@ -167,6 +167,7 @@ struct DocLayout {
   uint64_t* doc_len;
   Slot* arena;
   uint64_t* over_docs;
+  uint64_t* over_sorted;
   uint64_t total;
 };
 
@@ -199,6 +200,7 @@ void layout_docs(uint64_t len, uint64_t n_docs, const wc_opts* o, void* ws, DocL
   L->doc_len = B.take<uint64_t>(std::max<uint64_t>(n_docs, 1) * 8);
   L->arena = B.take<Slot>(L->arena_slots * sizeof(Slot));
   L->over_docs = B.take<uint64_t>(std::max<uint64_t>(n_docs, 1) * 8);
+  L->over_sorted = B.take<uint64_t>(std::max<uint64_t>(n_docs, 1) * 8);
   L->total = B.off;
 }
 
@@ -226,6 +228,7 @@ DocParams doc_params(const DocLayout& L, const wc_opts* o, uint32_t lds, uint32_
   P.cap_b = L.cap_b;
   P.arena = L.arena;
   P.over_docs = L.over_docs;
+  P.over_sorted = L.over_sorted;
   P.arena_slots = L.arena_slots;
   P.key_mask = key_mask_of(o);
   P.count_bias = o->debug_count_bias;

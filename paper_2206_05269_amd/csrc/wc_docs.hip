@@ -655,12 +655,48 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       const uint64_t q = s_item;
       __syncthreads();
       if (q >= n_over) break;
-      const uint64_t d = P.over_docs[q] & ~kDirectDoc;
-      if (tid == 0) s_direct = (P.over_docs[q] & kDirectDoc) != 0;
+      const uint64_t e = P.over_sorted[q];
+      const uint64_t d = e & kDocIdMask;
+      if (tid == 0) s_direct = (e & kDirectDoc) != 0;
       recount_doc((int64_t)offsets[d], (int64_t)offsets[d + 1], d);
     }
   }
   if (tid == 0) add64(&hdr->total_tokens, s_tokens);
+}
+
+// The second pass's queue, largest document first: a counting sort over power-of-two size
+// classes by one workgroup (each thread keeps the same entries in both passes). A workgroup
+// that took a large document last would otherwise finish the pass alone.
+__global__ __launch_bounds__(1024) void doc_order_kernel(DocParams P) {
+  constexpr uint32_t kClasses = 48;  // floor(log2(bytes)), largest first
+  __shared__ uint32_t s_cnt[kClasses], s_at[kClasses];
+  const uint64_t n = P.hdr->over_n;
+  const uint64_t* offsets = P.task->offsets;
+  if (threadIdx.x < kClasses) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint64_t q = threadIdx.x; q < n; q += blockDim.x) {
+    const uint64_t e = P.over_docs[q];
+    const uint64_t d = e & kDocIdMask;
+    const uint64_t b = offsets[d + 1] - offsets[d];
+    const uint32_t c = b ? 63u - (uint32_t)__clzll((long long)b) : 0u;
+    const uint32_t k = kClasses - 1 - min(c, kClasses - 1);
+    P.over_docs[q] = (e & (kDirectDoc | kDocIdMask)) | ((uint64_t)k << 56);
+    atomicAdd(&s_cnt[k], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0;
+    for (uint32_t k = 0; k < kClasses; ++k) {
+      s_at[k] = a;
+      a += s_cnt[k];
+    }
+  }
+  __syncthreads();
+  for (uint64_t q = threadIdx.x; q < n; q += blockDim.x) {
+    const uint64_t e = P.over_docs[q];
+    const uint32_t k = (uint32_t)(e >> 56) & 0x7fu;
+    P.over_sorted[atomicAdd(&s_at[k], 1u)] = e & (kDirectDoc | kDocIdMask);
+  }
 }
 
 __global__ void doc_finish_kernel(DocParams P) {
@@ -716,6 +752,7 @@ hipError_t launch_docs(const DocParams& P, uint32_t grid, size_t dyn, hipStream_
   hipLaunchKernelGGL(doc_validate_kernel, dim3(256), dim3(256), 0, s, P);
   hipLaunchKernelGGL(doc_windows_kernel, dim3(256), dim3(256), 0, s, P);
   hipLaunchKernelGGL((doc_kernel<kDocBlock, false>), dim3(grid), dim3(kDocBlock), dyn, s, P);
+  hipLaunchKernelGGL(doc_order_kernel, dim3(1), dim3(1024), 0, s, P);
   hipLaunchKernelGGL((doc_kernel<kDocBlock, true>), dim3(grid), dim3(kDocBlock), dyn, s, P);
   hipLaunchKernelGGL(doc_finish_kernel, dim3(1), dim3(64), 0, s, P);
   return hipGetLastError();

@@ -133,12 +133,16 @@ struct DocParams {
   uint64_t* doc_len;       // [n_docs]
   uint64_t cap_e, cap_b;
   Slot* arena;             // private tables of large documents
-  uint64_t* over_docs;     // [n_docs] documents for the second pass
+  uint64_t* over_docs;     // [n_docs] documents for the second pass, as queued
+  uint64_t* over_sorted;   // [n_docs] the same, largest first
   uint64_t arena_slots;
   uint64_t key_mask;
   uint64_t count_bias;     // added to every exported count (debug; 0 normally)
 };
-constexpr uint64_t kDirectDoc = 1ull << 63;  // over_docs entry: queued without a first count
+// second-pass queue entries: document index (bits 0-55), size class while the queue is sorted
+// (bits 56-62), queued without a first count (bit 63)
+constexpr uint64_t kDirectDoc = 1ull << 63;
+constexpr uint64_t kDocIdMask = (1ull << 56) - 1;
 size_t doc_dyn(uint32_t entries);  // dynamic LDS of the document kernel
 hipError_t set_doc_smem(size_t dyn);
 hipError_t launch_docs(const DocParams& P, uint32_t grid, size_t dyn, hipStream_t s);
