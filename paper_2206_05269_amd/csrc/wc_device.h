@@ -295,7 +295,11 @@ WC_DEV bool id_equal(const WordId& id, uint64_t s0, uint64_t s1, uint32_t sdoc1)
 // claims a slot publishes the slot's identity inside that iteration, before any lane of its
 // wave reads it; a lane that finds a claimed slot whose identity is not yet visible looks at
 // the same slot again in the next iteration rather than waiting. No lane waits on a lane.
-template <bool kPerDoc>
+// kCasFirst claims with a compare-and-swap without reading the key first: one round trip for
+// a new word, for tables where most inserts are new words and few lanes meet on one slot (a
+// document's private table); shared tables read first, so that hot words do not turn every
+// occurrence into an atomic on their slot.
+template <bool kPerDoc, bool kCasFirst = false>
 WC_DEV uint64_t table_insert(Slot* __restrict__ tab, uint64_t mask, uint64_t key,
                              const WordId& id, uint64_t n, Header* hdr, uint64_t occ_limit) {
   uint64_t i = key & mask;
@@ -307,7 +311,7 @@ WC_DEV uint64_t table_insert(Slot* __restrict__ tab, uint64_t mask, uint64_t key
     uint64_t k = 1;
     bool won = false;
     if (active) {
-      k = ld_relaxed(&s->key);
+      k = kCasFirst ? 0 : ld_relaxed(&s->key);
       if (k == 0) {
         k = cas64(&s->key, 0, key);
         won = (k == 0);

@@ -166,8 +166,12 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       if (!recount) {
         s_over[r] = 1;
       } else if (pok) {
-        table_insert<false>(priv, pmask, finish_key(fnv_packed(lo, hi, packed_len(lo, hi)), P.key_mask),
-                            short_id(lo, hi, 0), 1, hdr, ~0ull);
+        // (the key only places the word in this document's table, which the library alone
+        // reads: a multiply-xorshift of the packed bytes instead of FNV-1a's byte loop)
+        uint64_t k = (lo ^ ((hi << 29) | (hi >> 35))) * 0x9E3779B97F4A7C15ull;
+        k ^= k >> 31;
+        table_insert<false, true>(priv, pmask, finish_key(k, P.key_mask), short_id(lo, hi, 0), 1,
+                                  hdr, ~0ull);
       }
     };
     // one short word (lo, hi) of document r, all lanes that call it together
@@ -188,8 +192,8 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       } else if (!recount) {
         s_over[r] = 1;
       } else if (pok) {
-        table_insert<false>(priv, pmask, finish_key(h64, P.key_mask), long_id(corpus + start, n, 0),
-                            1, hdr, ~0ull);
+        table_insert<false, true>(priv, pmask, finish_key(h64, P.key_mask),
+                                  long_id(corpus + start, n, 0), 1, hdr, ~0ull);
       }
     };
     auto doc_end = [&](uint32_t r) -> uint64_t { return recount ? (uint64_t)B : s_doff[r + 1]; };
@@ -315,6 +319,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
           if (act && !sh2[x]) {
             const int64_t start = p0 - 16 + (int64_t)s2[x];
             long_word(start, wl2[x] ? (uint64_t)(start + wl2[x]) : doc_end(r2[x]), r2[x]);
+            wait_vmem();
           }
           if (!recount && sh2[x] && s_over[r2[x]]) sh2[x] = false;  // recounted later
         }
@@ -368,7 +373,10 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
         for (int x = 0; x < 2; ++x) {
           if (sh2[x]) {
             const uint64_t hr = recount ? hi2[x] : hi_with_doc(hi2[x], r2[x]);
-            if (!red_add(T, lo2[x], hr, h2[x])) overflow(lo2[x], hi2[x], r2[x]);
+            if (!red_add(T, lo2[x], hr, h2[x])) {
+              overflow(lo2[x], hi2[x], r2[x]);
+              if (recount) wait_vmem();
+            }
           }
         }
         wave_sync();

@@ -299,7 +299,9 @@ __global__ __launch_bounds__(BLOCK) void sample_kernel(GlobalParams P) {
 }
 
 // Count threshold of the selection: words with a sample count (clamped at 255) >= t fit the
-// dictionary (acc of them); `room` more may come from count t - 1.
+// dictionary (acc of them); `room` more may come from count t - 1. hist is an LDS copy of the
+// count histogram: from device memory, each step of the loop, which may stop at any count,
+// would wait for its own load.
 WC_DEV void dict_threshold(const uint32_t* hist, uint32_t cap, uint32_t* t, uint32_t* acc,
                            uint32_t* room) {
   uint32_t a = 0, th = 256;
@@ -334,9 +336,12 @@ __global__ __launch_bounds__(256) void dict_select_kernel(GlobalParams P) {
   __shared__ uint32_t s_t, s_acc, s_room, s_n[2], s_base[2];
   __shared__ uint4 s_key[2][kList];
   __shared__ uint32_t s_c[2][kList];
+  __shared__ uint32_t s_hist[256];
+  for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) s_hist[i] = P.dict->hist[i];
+  __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t t, acc, room;
-    dict_threshold(P.dict->hist, P.dict_cap, &t, &acc, &room);
+    dict_threshold(s_hist, P.dict_cap, &t, &acc, &room);
     s_t = t;
     s_acc = acc;
     s_room = room;
@@ -402,10 +407,13 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
   __shared__ uint16_t s_slot[kDictSlots];
   __shared__ uint16_t s_disp[kDispBuckets];
   __shared__ uint32_t s_n, s_placed;
+  __shared__ uint32_t s_hist[256];
   const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < 256; i += blockDim.x) s_hist[i] = P.dict->hist[i];
+  __syncthreads();
   if (tid == 0) {
     uint32_t t, acc, room;
-    dict_threshold(P.dict->hist, P.dict_cap, &t, &acc, &room);
+    dict_threshold(s_hist, P.dict_cap, &t, &acc, &room);
     const uint32_t low = P.dict->n_low;
     s_n = acc + (low < room ? low : room);
     s_placed = 0;
@@ -697,8 +705,10 @@ __global__ __launch_bounds__(BLOCK) void global_map_kernel(GlobalParams P) {
     }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
-      if (lane + 64 * x < nw && !f2[x])
+      if (lane + 64 * x < nw && !f2[x]) {
         long_token(p0, s2[x], n2[x] ? s2[x] + n2[x] - 1 : kLongEnd);
+        wait_vmem();
+      }
     // each LDS step reads for both tokens before either waits (pin)
     PackSrc ps[2];
     uint4 lm[2];

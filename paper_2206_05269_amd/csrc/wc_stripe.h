@@ -149,6 +149,13 @@ WC_DEV uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
+// Waits for every device-memory access of the wave (vmcnt 0; the other counters left alone).
+// Ending a rarely taken branch with it keeps the compiler from waiting where the branch
+// rejoins: it cannot tell which of the wave's loads are still in flight on the branch's path,
+// and would otherwise make every wave, branch taken or not, wait there for all of them (the
+// next stripe's text included).
+WC_DEV void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Orders this wave's LDS accesses around the point in the compiler (the hardware keeps one
 // wave's LDS operations in order).
 WC_DEV void wave_sync() {
