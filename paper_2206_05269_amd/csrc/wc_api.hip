@@ -221,6 +221,8 @@ DocParams doc_params(const DocLayout& L, const wc_opts* o, uint32_t lds, uint32_
   P.counts = L.counts;
   P.count_bytes = o->count_bytes;
   P.lds_entries = lds;
+  P.rc_entries = recount_entries();
+  P.pad1 = 0;
   P.docs = L.docs;
   P.doc_ptr = L.doc_ptr;
   P.doc_len = L.doc_len;

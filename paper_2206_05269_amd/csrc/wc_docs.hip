@@ -116,13 +116,15 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   const uint64_t win = P.win_bytes;
   const uint64_t n_win = len / win + 1;
 
-  const uint32_t E = P.lds_entries;
+  // the second pass has no overflow threshold: its table fills all of its (more) entries,
+  // and the words that find no room go to the document's private table
+  const uint32_t E = kRecount ? P.rc_entries : P.lds_entries;
   RedTable T;
   T.slot = (uint32_t*)s_dyn;
   T.key = (uint4*)(T.slot + kRedSlots);
   T.cnt = (uint32_t*)(T.key + E);
   T.n = &s_nent;
-  T.cap = min(P.lds_cap, E);
+  T.cap = kRecount ? E : min(P.lds_cap, E);
   T.stall = hdr;  // a word must never be both in the LDS table and in a private table
   for (uint32_t i = tid; i < kRedSlots; i += BLOCK) T.slot[i] = 0;
   for (uint32_t i = tid; i < E; i += BLOCK) {
@@ -747,12 +749,32 @@ __global__ void doc_validate_kernel(DocParams P) {
   }
 }
 
+// The second pass's table takes what LDS its instance's static arrays leave (device limit per
+// workgroup minus static size, less the slots), in whole multiples of 64 entries, at most
+// what 13-bit entry indices reach; kDocLds when the attributes cannot be read.
+uint32_t recount_entries() {
+  static const uint32_t e = [] {
+    int dev = 0, lim = 0;
+    hipFuncAttributes a;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipFuncGetAttributes(&a, (const void*)doc_kernel<kDocBlock, true>) != hipSuccess)
+      return kDocLds;
+    const int64_t room = (int64_t)lim - (int64_t)a.sharedSizeBytes - (int64_t)kRedSlots * 4;
+    int64_t n = room / 20 / 64 * 64;
+    if (n > 8128) n = 8128;
+    return n < (int64_t)kDocLds ? kDocLds : (uint32_t)n;
+  }();
+  return e;
+}
+
 hipError_t set_doc_smem(size_t dyn) {
   hipError_t e = hipFuncSetAttribute((const void*)doc_kernel<kDocBlock, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)doc_kernel<kDocBlock, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)doc_dyn(recount_entries()));
   return e;
 }
 
@@ -761,7 +783,8 @@ hipError_t launch_docs(const DocParams& P, uint32_t grid, size_t dyn, hipStream_
   hipLaunchKernelGGL(doc_windows_kernel, dim3(256), dim3(256), 0, s, P);
   hipLaunchKernelGGL((doc_kernel<kDocBlock, false>), dim3(grid), dim3(kDocBlock), dyn, s, P);
   hipLaunchKernelGGL(doc_order_kernel, dim3(1), dim3(1024), 0, s, P);
-  hipLaunchKernelGGL((doc_kernel<kDocBlock, true>), dim3(grid), dim3(kDocBlock), dyn, s, P);
+  hipLaunchKernelGGL((doc_kernel<kDocBlock, true>), dim3(grid), dim3(kDocBlock),
+                     doc_dyn(P.rc_entries), s, P);
   hipLaunchKernelGGL(doc_finish_kernel, dim3(1), dim3(64), 0, s, P);
   return hipGetLastError();
 }

@@ -138,12 +138,15 @@ struct DocParams {
   uint64_t arena_slots;
   uint64_t key_mask;
   uint64_t count_bias;     // added to every exported count (debug; 0 normally)
+  uint32_t rc_entries;     // second pass: LDS table entries (all of them usable)
+  uint32_t pad1;
 };
 // second-pass queue entries: document index (bits 0-55), size class while the queue is sorted
 // (bits 56-62), queued without a first count (bit 63)
 constexpr uint64_t kDirectDoc = 1ull << 63;
 constexpr uint64_t kDocIdMask = (1ull << 56) - 1;
 size_t doc_dyn(uint32_t entries);  // dynamic LDS of the document kernel
+uint32_t recount_entries();         // LDS entries of its second pass (the most that fit)
 hipError_t set_doc_smem(size_t dyn);
 hipError_t launch_docs(const DocParams& P, uint32_t grid, size_t dyn, hipStream_t s);
 
