@@ -90,9 +90,10 @@ typedef struct wc_tuning {
   uint32_t grid_blocks;   /* workgroups in the count launch (0 = 2 per CU) */
   uint32_t lds_load_pct;  /* LDS table load at which it is flushed (one-pass kernel) or at
                              which a document counts as overflowed (document-centric kernel:
-                             it is then counted again with a private table); 0 = default */
+                             it is then counted again with a private table); 0 = default
+                             (50 % for the one-pass kernel, 85 % for the document-centric) */
   uint32_t chunk_bytes;   /* per-document mode: bytes per work item, power of two in
-                             16 KiB..1 MiB (0 = 64 KiB) */
+                             16 KiB..1 MiB (0 = 32 KiB) */
   uint32_t direct_kib;    /* per-document mode, document-centric kernel: a document longer
                              than chunk_bytes and than this many KiB skips the first,
                              optimistic count (in which it would likely overflow the LDS
@@ -292,7 +293,7 @@ wc_status wc_topk_ratio(const wc_result* const* corpora, uint32_t n_corpora, uin
 
 /* Batched per-document counting (Section 3.1 counts every document in its own dictionary):
  * all documents of a corpus are counted into per-document tables by one persistent launch
- * that takes 64 KiB windows of documents from a device-side queue. The first wc_batch_run
+ * that takes 32 KiB windows of documents from a device-side queue. The first wc_batch_run
  * captures the whole call (task upload, clears, kernels, size readback) into a HIP graph; later
  * runs only update a pinned host task description and replay the graph, so a run makes no
  * allocation and one graph launch. Device memory is the caller's workspace of
@@ -376,8 +377,10 @@ uint64_t wc_server_launches(wc_server* s);
 wc_status wc_server_destroy(wc_server* s);
 
 /* Autotuner: time wc_count on a calibration sample (device-resident, as wc_count) for each
- * point of a small grid of launch tunings (per-document mode: work-item bytes x LDS entries x
- * LDS load; global mode: LDS entries x flush load x flush policy) with HIP events on
+ * point of a small grid of launch tunings (per-document mode: one point, 32 KiB work items
+ * with 4096 LDS entries at an 85 % load, which a calibration sample of a few thousand
+ * documents cannot rank against others; global mode: LDS entries x flush load x flush
+ * policy) with HIP events on
  * `stream`, and return the
  * fastest in *best (its time per call in *best_ms). The workspace must hold
  * wc_autotune_plan() bytes. The sample's counts are not returned. Output and private-table

@@ -207,7 +207,7 @@ void layout_docs(uint64_t len, uint64_t n_docs, const wc_opts* o, void* ws, DocL
 DocParams doc_params(const DocLayout& L, const wc_opts* o, uint32_t lds, uint32_t pct,
                      uint32_t chunk, uint32_t direct_kib) {
   DocParams P;
-  P.lds_cap = (uint32_t)((uint64_t)lds * (pct ? pct : 75) / 100);
+  P.lds_cap = (uint32_t)((uint64_t)lds * (pct ? pct : 85) / 100);
   if (P.lds_cap < 1) P.lds_cap = 1;
   if (P.lds_cap > lds - lds / 8) P.lds_cap = lds - lds / 8;
   P.direct_kib = direct_kib;
@@ -1138,9 +1138,13 @@ namespace {
 std::vector<wc_tuning> tune_grid(const wc_opts* o) {
   std::vector<wc_tuning> g;
   if (o->mode == WC_PER_DOC) {
-    for (uint32_t chunk : {32u << 10, 64u << 10, 128u << 10})
-      for (uint32_t lds : {2048u, 4096u})
-        for (uint32_t pct : {60u, 85u}) g.push_back(wc_tuning{0, lds, 0, 0, pct, chunk, 0});
+    // One point: 32 KiB work items, the full LDS table at the highest load. On a calibration
+    // sample of a few thousand documents the second pass lasts as long as its largest
+    // document, whatever else it counts, so the sample favours points that send more
+    // documents there: it chose a smaller table and load (batched-100k 21.7 ms, nearly every
+    // document counted twice instead of 8,400) or 16 KiB items (15.1 ms, 24,600) over this
+    // point (13.1 ms); 64 KiB items overflow the default private-table arena.
+    g.push_back(wc_tuning{0, 4096, 0, 0, 85, 32u << 10, 0});
   } else {
     // one-pass kernel: LDS entries x flush load x flush policy (the two-pass kernels, from
     // 256 MiB, take lds_entries as the dictionary size and ignore the rest)

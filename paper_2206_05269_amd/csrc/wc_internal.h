@@ -103,7 +103,7 @@ hipError_t set_global_smem(uint32_t dict_cap, uint32_t reduce_entries);
 hipError_t launch_global(const GlobalParams& P, hipEvent_t a, hipEvent_t b, hipStream_t s);
 
 // per-document count (wc_docs.hip)
-constexpr uint64_t kWin = 64 * 1024;   // default bytes per work item window
+constexpr uint64_t kWin = 32 * 1024;   // default bytes per work item window
 constexpr uint64_t kMinWin = 16 * 1024;
 constexpr uint32_t kDocW = 256;        // documents per sub-window
 constexpr uint32_t kDocLds = 4096;     // LDS table entries (20 bytes each, beside 8192 slots)
