@@ -387,13 +387,18 @@ __global__ __launch_bounds__(256) void dict_select_kernel(GlobalParams P) {
   }
 }
 
-// One workgroup builds the perfect hash of the selected words (hash and displace, after
-// Belazzougui, Botelho and Dietzfelbinger): words are grouped by the low 9 bits of their hash;
-// each of 16 waves fills one region of 256 slots with its 32 groups, largest first, and a group
+// kBuildGroups workgroups build the perfect hash of the selected words (hash and displace,
+// after Belazzougui, Botelho and Dietzfelbinger): each groups all the words by the low bits of
+// their hash, then its 16 waves fill its share of the 256-slot regions, one region per wave,
+// each region with its 32 groups one after another, largest first (the placement was 135 of
+// the 167 us of one workgroup filling two regions per wave); a group
 // takes the first displacement that sends all of its words to free slots. Inside a group the
 // hottest words come first; a word that cannot be placed with the others (the same slot field
 // as a hotter word of its group in both fields, or no free displacement) is left out of the
 // dictionary, which only moves its counting to the partitions.
+constexpr uint32_t kBuildGroups = 2;
+static_assert(kDictRegions % kBuildGroups == 0 && kDictRegions / kBuildGroups <= 16,
+              "whole regions per workgroup, at most one per wave");
 __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
   constexpr uint32_t kMaxGroup = 64;  // words of one group placed at most (one per lane)
   constexpr uint32_t kRegionGroups = kDispBuckets / kDictRegions;
@@ -469,8 +474,10 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
   }
   __syncthreads();
   const uint32_t lane = tid & 63;
-  // wave v fills regions v, v + 16, ...
-  for (uint32_t r = tid >> 6; r < kDictRegions; r += blockDim.x / 64) {
+  // this workgroup's regions [r0, r1); wave v fills regions r0 + v, r0 + v + 16, ...
+  const uint32_t per_wg = kDictRegions / gridDim.x;
+  const uint32_t r0 = blockIdx.x * per_wg, r1 = r0 + per_wg;
+  for (uint32_t r = r0 + (tid >> 6); r < r1; r += blockDim.x / 64) {
     // the region's groups g = r + 16 L, largest first
     const uint32_t my_n = lane < kRegionGroups ? s_gn[r + kDictRegions * lane] : 0u;
     uint32_t rank = 0;
@@ -547,13 +554,18 @@ __global__ __launch_bounds__(1024) void dict_build_kernel(GlobalParams P) {
     if (lane == 0) atomicAdd(&s_placed, placed);
   }
   __syncthreads();
-  for (uint32_t i = tid; i < kDispBuckets; i += blockDim.x) P.dict->disp[i] = s_disp[i];
-  for (uint32_t i = tid; i < kDictSlots; i += blockDim.x) P.dict->slot[i] = s_slot[i];
+  // the displacements of this workgroup's groups (g mod kDictRegions in [r0, r1)) and the
+  // slots of its regions; the placed counts add up (the image and the header start at zero)
+  for (uint32_t i = tid; i < kDispBuckets; i += blockDim.x)
+    if ((i & (kDictRegions - 1)) - r0 < per_wg) P.dict->disp[i] = s_disp[i];
+  for (uint32_t i = r0 * 256 + tid; i < r1 * 256; i += blockDim.x) P.dict->slot[i] = s_slot[i];
   if (tid == 0) {
-    P.dict->keys[n] = make_uint4(0, 0, 0, 0);
-    P.dict->n = n;
-    P.dict->placed = s_placed;
-    P.hdr->stat[2] = s_placed;
+    if (blockIdx.x == 0) {
+      P.dict->keys[n] = make_uint4(0, 0, 0, 0);
+      P.dict->n = n;
+    }
+    atomicAdd(&P.dict->placed, s_placed);
+    add64(&P.hdr->stat[2], s_placed);
   }
 }
 
@@ -1133,7 +1145,7 @@ hipError_t launch_global(const GlobalParams& P, hipEvent_t a, hipEvent_t b, hipS
                              0, s, P);
   hipLaunchKernelGGL(dict_hist_kernel, dim3(256), dim3(256), 0, s, P);
   hipLaunchKernelGGL(dict_select_kernel, dim3(256), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(dict_build_kernel, dim3(1), dim3(1024), 0, s, P);
+  hipLaunchKernelGGL(dict_build_kernel, dim3(kBuildGroups), dim3(1024), 0, s, P);
   if (a) {
     hipError_t e = hipEventRecord(a, s);
     if (e != hipSuccess) return e;
