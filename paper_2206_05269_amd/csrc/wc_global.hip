@@ -292,7 +292,12 @@ __global__ __launch_bounds__(BLOCK) void sample_kernel(GlobalParams P) {
     }
   }
   __syncthreads();
-  for (uint32_t i = tid; i < kSampleLds; i += BLOCK) {
+  // Every workgroup's LDS table has the same layout (same hash, same size), so a hot word sits
+  // at the same entry in all of them: walked in entry order, all workgroups would add to its
+  // device slot at once. Each starts its walk at its own entry.
+  const uint32_t rot = (blockIdx.x * 1031u) & (kSampleLds - 1);
+  for (uint32_t j = tid; j < kSampleLds; j += BLOCK) {
+    const uint32_t i = (j + rot) & (kSampleLds - 1);
     const uint32_t c = s_cnt[i];
     if (c) sample_insert(P.sample_table, kSampleSlots - 1, s_lo[i], s_hi[i] & ~kTop, c);
   }
