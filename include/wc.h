@@ -97,7 +97,7 @@ typedef struct wc_tuning {
   uint32_t direct_kib;    /* per-document mode, document-centric kernel: a document longer
                              than chunk_bytes and than this many KiB skips the first,
                              optimistic count (in which it would likely overflow the LDS
-                             table) and is counted once, by the second pass (0 = twice
+                             table) and is counted once, by the second pass (0 = 9/4 of
                              chunk_bytes; WC_DIRECT_NEVER = no document skips it) */
 } wc_tuning;
 

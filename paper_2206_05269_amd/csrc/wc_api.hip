@@ -87,7 +87,7 @@ bool resolve_tuning(const wc_tuning* t, Tune* out) {
   u.chunk = t && t->chunk_bytes ? t->chunk_bytes : (uint32_t)kWin;
   if (!is_pow2(u.chunk) || u.chunk < kMinWin || u.chunk > (1u << 20)) return false;
   const uint32_t dk = t ? t->direct_kib : 0u;
-  u.direct_kib = dk == WC_DIRECT_NEVER ? 0u : dk ? dk : 2 * (u.chunk >> 10);
+  u.direct_kib = dk == WC_DIRECT_NEVER ? 0u : dk ? dk : (u.chunk >> 10) * 9 / 4;
   *out = u;
   return true;
 }
