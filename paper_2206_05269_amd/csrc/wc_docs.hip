@@ -604,9 +604,18 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   };
 
   if constexpr (!kRecount) {
+    // Thread 0 takes the next item as soon as it publishes the current one, so the atomic's
+    // round trip overlaps the current item's work instead of starting the next item.
+    uint64_t next = 0;
+    if (tid == 0) next = __hip_atomic_fetch_add(&hdr->work_next, 1ull, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
     while (true) {
-      if (tid == 0) s_item = __hip_atomic_fetch_add(&hdr->work_next, 1ull, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) {
+        s_item = next;
+        if (next < n_win)
+          next = __hip_atomic_fetch_add(&hdr->work_next, 1ull, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+      }
       __syncthreads();
       const uint64_t w = s_item;
       __syncthreads();
@@ -615,13 +624,14 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       const uint64_t db = min(P.win_doc[w + 1], n_docs);
       for (uint64_t d0 = da; d0 < db; d0 += kDocW) {
         const uint32_t nd = (uint32_t)min((uint64_t)kDocW, db - d0);
-        // a document longer than the window is the last of its item: it is counted alone
-        // after the others, with the whole LDS table to itself
-        const bool big = offsets[d0 + nd] - offsets[d0 + nd - 1] > win;
-        const uint32_t ns = big ? nd - 1 : nd;
         for (uint32_t i = tid; i <= nd; i += BLOCK) s_doff[i] = offsets[d0 + i];
         for (uint32_t i = tid; i < nd; i += BLOCK) s_over[i] = 0;
         __syncthreads();
+        // a document longer than the window is the last of its item: it is counted alone
+        // after the others, with the whole LDS table to itself
+        const uint64_t last_len = s_doff[nd] - s_doff[nd - 1];
+        const bool big = last_len > win;
+        const uint32_t ns = big ? nd - 1 : nd;
         if (ns > 0) {
           const int64_t A = (int64_t)s_doff[0], B = (int64_t)s_doff[ns];
           if (A < B) scan(A, B, ns);
@@ -630,8 +640,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
           clear_table();
           queue_over(ns, d0);
         }
-        if (big && P.direct_kib &&
-            offsets[d0 + nd] - offsets[d0 + nd - 1] > ((uint64_t)P.direct_kib << 10)) {
+        if (big && P.direct_kib && last_len > ((uint64_t)P.direct_kib << 10)) {
           // large enough to overflow the LDS table: straight to the second pass, which also
           // counts its tokens
           if (tid == 0) {
@@ -658,9 +667,16 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
     }
   } else {
     const uint64_t n_over = hdr->over_n;
+    uint64_t next = 0;  // as in the first pass: the next queue position is taken early
+    if (tid == 0) next = __hip_atomic_fetch_add(&hdr->over_next, 1ull, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
     while (true) {
-      if (tid == 0) s_item = __hip_atomic_fetch_add(&hdr->over_next, 1ull, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) {
+        s_item = next;
+        if (next < n_over)
+          next = __hip_atomic_fetch_add(&hdr->over_next, 1ull, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+      }
       __syncthreads();
       const uint64_t q = s_item;
       __syncthreads();
