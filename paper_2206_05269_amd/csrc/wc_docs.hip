@@ -20,11 +20,14 @@
 // and word bytes are contiguous and the word offsets stay a valid CSR over the whole output.
 //
 // A document longer than the window is always the last of its item; it is counted after the
-// others, alone, with the whole LDS table to itself. Documents that still overflow are queued
-// for a second launch, which counts each one with a whole workgroup: the LDS table first, then
-// a private open-addressing table in device memory (taken from an arena, cleared by the
-// workgroup, sized from the document's length) for the words that find no room; the LDS
-// entries are then added to the private table, which is compacted into the output.
+// others, alone, with the whole LDS table to itself, unless it is also longer than the size
+// limit (direct_kib): then it skips this pass. Such documents, and those that overflow, are
+// queued for a second launch. Its queue is first sorted by size, largest first; then each
+// document is counted by a whole workgroup: an LDS table with no overflow threshold (as many
+// entries as the instance's LDS holds), then a private open-addressing table in device memory
+// (taken from an arena, cleared by the workgroup, sized from the document's length) for the
+// words that find no room. The entries of both tables are written out side by side with one
+// reservation (a private word that also reached the LDS table is merged into its entry).
 //
 // Every size the kernels need is read from a device-side task description, so a whole call
 // can be captured once in a HIP graph and replayed for other corpora.
