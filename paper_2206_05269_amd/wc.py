@@ -203,8 +203,8 @@ class Table:
     def stats(self) -> dict:
         """Per-call statistics: the two-pass global count's spilled records, records sent
         straight to the global table, dictionary words and pass-2 overflow; the
-        document-centric kernel's documents counted again with a private table (zero where a
-        path has none)."""
+        document-centric kernel's documents counted by its second pass (overflowed, or over the
+        size limit; zero where a path has none)."""
         s = self.res.stats
         return {"spilled": int(s[0]), "arena_direct": int(s[1]), "dict_words": int(s[2]),
                 "docs_recounted": int(s[3]), "reduce_overflow": int(s[4])}
