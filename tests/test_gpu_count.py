@@ -396,6 +396,25 @@ def test_per_doc_long_words_and_collisions():
         check(text, off, per_doc=True, debug_hash_bits=bits, tuning=wc.make_tuning(lds_entries=256))
 
 
+@pytest.mark.parametrize("bits,direct", [(0, wc.WC_DIRECT_NEVER), (3, wc.WC_DIRECT_NEVER), (3, 0)])
+def test_per_doc_private_table_collisions(bits, direct):
+    """A document with more distinct words (9,000) than the second pass's LDS table holds: the
+    rest go to its private table in device memory, claimed with a compare-and-swap first; with
+    debug_hash_bits=3 every private key is one of eight values, so inserts probe far and tell
+    words apart by their bytes. The document reaches the second pass by overflowing the first
+    (WC_DIRECT_NEVER) or by its size (default limit)."""
+    words = [b"w%05d" % i for i in range(9000)]
+    rng = np.random.default_rng(5)
+    doc = b" ".join(words + [words[i] for i in rng.integers(0, 9000, 6000)])
+    text, off = join_docs([b"a b c", doc, b"tail words here a"])
+    tu = wc.make_tuning(direct_kib=direct)
+    check(text, off, per_doc=True, debug_hash_bits=bits, debug_flags=wc.WC_DEBUG_DOCS, tuning=tu)
+    t, o = to_dev(text, off)
+    got = wc.count(t, o, per_doc=True, count_bytes=4, debug_hash_bits=bits,
+                   debug_flags=wc.WC_DEBUG_DOCS, tuning=tu)
+    assert got.stats["docs_recounted"] >= 1
+
+
 def test_per_doc_kernel_choice():
     """By default the document-centric kernel runs for documents averaging at most 64 KiB and
     the one-pass (document, word) table above that; both give the oracle's tables."""
