@@ -102,6 +102,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
   __shared__ uint32_t s_nent, s_tmp[NW];
   __shared__ uint64_t s_item, s_e0, s_b0, s_pbase;
   __shared__ uint32_t s_pslots;
+  __shared__ uint32_t s_pused;  // second pass: a word of the document went to its private table
   __shared__ unsigned long long s_tokens;
   __shared__ uint32_t s_direct;  // second pass: the document was queued without a first count
   static_assert(kWaveStarts / 2 + kEndWords <= kWaveStarts, "starts and ends fit a wave's list");
@@ -171,6 +172,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       if (!recount) {
         s_over[r] = 1;
       } else if (pok) {
+        s_pused = 1;
         // (the key only places the word in this document's table, which the library alone
         // reads: a multiply-xorshift of the packed bytes instead of FNV-1a's byte loop)
         uint64_t k = (lo ^ ((hi << 29) | (hi >> 35))) * 0x9E3779B97F4A7C15ull;
@@ -197,6 +199,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       } else if (!recount) {
         s_over[r] = 1;
       } else if (pok) {
+        s_pused = 1;
         table_insert<false, true>(priv, pmask, finish_key(h64, P.key_mask),
                                   long_id(corpus + start, n, 0), 1, hdr, ~0ull);
       }
@@ -505,6 +508,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       }
       s_pbase = base;
       s_pslots = (uint32_t)slots;
+      s_pused = 0;
       s_dcur[0] = 0;
     }
     __syncthreads();
@@ -515,6 +519,9 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
     __syncthreads();
     if (A < B) scan(A, B, 1);
     __syncthreads();
+    // the private table is read back only when a word went there (most documents fit the
+    // LDS table; their cleared private table would be read twice for nothing)
+    const uint32_t pslots = s_pused ? slots : 0u;
     // the document's entries and word bytes: LDS entries with a count, private slots in use
     const uint32_t ne = min(s_nent, T.cap);
     uint64_t part = 0;
@@ -530,7 +537,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
       const uint4 k = key4(sl.w0, sl.w1 & ~kTop);
       return red_find(T, k, red_hash(k));
     };
-    for (uint32_t i = tid; i < slots; i += BLOCK) {
+    for (uint32_t i = tid; i < pslots; i += BLOCK) {
       const Slot sl = t[i];
       if (!sl.key) continue;
       const int li = in_lds(sl);
@@ -583,7 +590,7 @@ __global__ __launch_bounds__(BLOCK) void doc_kernel(DocParams P) {
         const uint64_t hi = (uint64_t)k.z | ((uint64_t)k.w << 32);
         put(lo, hi, packed_len(lo, hi), c, nullptr);
       }
-      for (uint32_t i = tid; i < slots; i += BLOCK) {
+      for (uint32_t i = tid; i < pslots; i += BLOCK) {
         const Slot sl = t[i];
         if (!sl.key || in_lds(sl) >= 0) continue;
         const bool lng = (sl.w0 & kTop) != 0;
